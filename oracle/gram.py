@@ -1,0 +1,72 @@
+"""Trajectory-only Gram quantities (oracle, FP64).
+
+The paper's matrix (Section 3.4, Eq. DG; Appendix A.1, Eq. AnnMatG):
+
+    G[u, v] = (1/N^2) * sum_l exp(+i 2 pi (kx_l u + ky_l v)),  u, v in [1-N, N-1]
+
+For the image-domain Gram operator Q = A^H A with x[n, m] (row n <-> ky):
+
+    (Q x)[n, m] = sum_{n', m'} (1/N^2) sum_l exp(i 2 pi (kx (m'-m) + ky (n'-n))) x[n', m']
+                = sum_{a, b} h[a, b] x[n - a, m - b]
+
+a linear convolution with the lag kernel
+
+    h[a, b] = (1/N^2) * sum_l exp(-i 2 pi (ky_l a + kx_l b)) = G[-b, -a],
+
+a, b in [-(N-1), N-1].  G and h are conjugate centro-symmetric
+(h[-a, -b] = conj h[a, b]); the paper calls this a Hermitian symmetry.
+
+``khat`` places h circularly on an L x L grid (lag a at index a mod L,
+other slots zero) and takes its 2D DFT; because of the conjugate symmetry the
+spectrum is real, and the linear convolution is exact for L >= 2N - 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_CHUNK = 4096
+
+
+def lag_kernel(k: np.ndarray, N: int) -> np.ndarray:
+    """h as complex128 [2N-1, 2N-1], entry [a + N-1, b + N-1]."""
+    lags = np.arange(-(N - 1), N, dtype=np.float64)
+    h = np.zeros((2 * N - 1, 2 * N - 1), dtype=np.complex128)
+    M = k.shape[0]
+    for s in range(0, M, _CHUNK):
+        e = min(M, s + _CHUNK)
+        Fy = np.exp(-2j * np.pi * np.outer(k[s:e, 1], lags))   # [c, a]
+        Fx = np.exp(-2j * np.pi * np.outer(k[s:e, 0], lags))   # [c, b]
+        h += Fy.T @ Fx
+    return h / (N * N)
+
+
+def paper_G(k: np.ndarray, N: int) -> np.ndarray:
+    """The paper's G as complex128 [2N-1, 2N-1], entry [u + N-1, v + N-1]."""
+    lags = np.arange(-(N - 1), N, dtype=np.float64)
+    G = np.zeros((2 * N - 1, 2 * N - 1), dtype=np.complex128)
+    M = k.shape[0]
+    for s in range(0, M, _CHUNK):
+        e = min(M, s + _CHUNK)
+        Ex = np.exp(2j * np.pi * np.outer(k[s:e, 0], lags))    # [c, u]
+        Ey = np.exp(2j * np.pi * np.outer(k[s:e, 1], lags))    # [c, v]
+        G += Ex.T @ Ey
+    return G / (N * N)
+
+
+def circulant_embed(h: np.ndarray, N: int, L: int) -> np.ndarray:
+    """L x L array with h[a, b] at [a mod L, b mod L] (requires L >= 2N-1)."""
+    if L < 2 * N - 1:
+        raise ValueError("L must be >= 2N-1")
+    c = np.zeros((L, L), dtype=np.complex128)
+    idx = np.arange(-(N - 1), N) % L
+    c[np.ix_(idx, idx)] = h
+    return c
+
+
+def khat(k: np.ndarray, N: int, L: int, h: np.ndarray | None = None,
+         return_complex: bool = False) -> np.ndarray:
+    """Real L x L spectrum of the circulant-embedded lag kernel."""
+    if h is None:
+        h = lag_kernel(k, N)
+    K = np.fft.fft2(circulant_embed(h, N, L))
+    return K if return_complex else K.real.copy()
