@@ -1,0 +1,242 @@
+"""Benchmark: regularised spiral-MRI reconstruction on one MI355X.
+
+Workload (default): 256 x 256 complex images, 16-interleave Archimedean
+spiral at 2x angular undersampling (M = 32768 samples), hyperbolic penalty
+delta = 0.02, lambda = 0.01, 300 pseudo-CG iterations, noise sigma =
+0.02 max|y|; a batch of B frames (default 128) sharing the trajectory.
+
+One step = the whole hot path for one batch: plan (trajectory upload and
+phasor tables), FP64 Gram kernel and its spectrum, adjoint b = A^H y, 300
+iterations (Toeplitz Gram apply, penalty stencil, step length, updates),
+objective and statistics, and the forward model of the result (data
+consistency).  Inputs are resident in device memory when the timed region
+starts.  value = reconstructions per second over the timed steps.
+
+Prints one JSON line (see the metric contract in the repository docs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synthetic  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "recons/sec + p50/p99 latency at 256^2 spiral, rel-L2<=1e-4 vs FP64 oracle"
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def colpass_bytes(N: int, L: int, B: int) -> float:
+    """Algorithmic HBM bytes of one column-pass launch over B frames:
+    read and write the N x L complex64 intermediate per frame (16 N L bytes)
+    and read the L x L FP32 spectrum once (4 L^2)."""
+    return B * 16.0 * N * L + 4.0 * L * L
+
+
+def kernel_bytes(kind: str, N: int, L: int, B: int) -> float:
+    img = 8.0 * N * N  # one complex64 image
+    if kind == "colpass":
+        return colpass_bytes(N, L, B)
+    if kind == "dir_rowfft":   # read g, d_old, x; write d, T (N x L)
+        return B * (3 * img + img + 8.0 * N * L)
+    if kind == "rowifft":      # read T, d; write Qd
+        return B * (8.0 * N * L + 2 * img)
+    if kind == "update":       # read x, d, r, Qd, g; write x, r, g
+        return B * 8 * img
+    raise ValueError(kind)
+
+
+def synth_batch(plan, prob, B, torch):
+    """y = A x_true + sigma * noise per frame, on the GPU (input synthesis)."""
+    x_true = torch.from_numpy(prob.x_true.astype(np.complex64)).cuda()
+    y0 = plan.forward(x_true)
+    noise = torch.from_numpy(prob.noise.astype(np.complex64)).cuda()
+    sig = prob.noise_c * y0.abs().amax(dim=1, keepdim=True)
+    return (y0 + sig * noise).contiguous()
+
+
+def cpu_baseline(args, torch, recon):
+    """The FP64 oracle on one 256^2 frame (adjoint + Gram + all iterations),
+    timed on the host, and the GPU result on the same frame against it."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    prob = synthetic.make_problem(2)
+    y = prob.measured(oracle.forward(prob.x_true, prob.k))
+    t0 = time.perf_counter()
+    b = oracle.adjoint(y[0], prob.k, prob.N)
+    K = oracle.khat(prob.k, prob.N, prob.L)
+    xo = oracle.solve(b, K, prob.lam, prob.delta, prob.iters)
+    dt = time.perf_counter() - t0
+    # GPU on the identical frame (oracle-made data)
+    plan = recon.Plan(prob.k, prob.N, prob.L)
+    plan.gram_kernel()
+    xg, st = plan.solve(torch.from_numpy(y.astype(np.complex64)).cuda(), prob.lam, prob.delta,
+                        prob.iters)
+    torch.cuda.synchronize()
+    xg = xg.cpu().numpy()[0].astype(np.complex128)
+    rel = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    return dict(value=1.0 / dt, unit="recons/sec", cores=int(threads), kind="oracle",
+                sample=(f"one 256x256 frame, M={prob.M}: adjoint + Gram kernel + "
+                        f"{prob.iters} iterations in FP64 numpy ({dt:.1f} s)"),
+                seconds=dt), rel
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--trace", default="colpass",
+                    choices=["colpass", "dir_rowfft", "rowifft", "update"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(frames and requests shard across GPUs with no exchange; "
+                                   "see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_0908_3252_amd import recon
+    recon.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    B = args.batch
+    prob = synthetic.make_frames(3, frames=B)  # 256^2, M = 32768, drifting phantoms
+    iters = args.iters or prob.iters
+    N, L, M = prob.N, prob.L, prob.M
+    log(f"workload N={N} M={M} L={L} B={B} iters={iters}")
+
+    # device-resident inputs and buffers (allocated once)
+    lib = recon.load()
+    plan = recon.Plan(prob.k, N, L)
+    plan.gram_kernel()
+    y = synth_batch(plan, prob, B, torch)
+    k_host = np.ascontiguousarray(prob.k)
+    plan_bytes = lib.recon_plan_bytes(M, N, L, 0)
+    gws_bytes = lib.recon_gram_workspace_bytes(M, N, L)
+    gws = torch.empty(gws_bytes, dtype=torch.uint8, device="cuda")
+    ws, ws_bytes = plan.workspace(B)
+    x = torch.empty((B, N, N), dtype=torch.complex64, device="cuda")
+    yfit = torch.empty((B, M), dtype=torch.complex64, device="cuda")
+    stats = torch.empty(B * recon.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    import ctypes
+
+    def step():
+        h = ctypes.c_void_p()
+        recon._check(lib.recon_plan(k_host.ctypes.data, M, N, L, 0, plan.mem.data_ptr(),
+                                    plan_bytes, stream, ctypes.byref(h)))
+        try:
+            recon._check(lib.recon_gram_kernel(h, gws.data_ptr(), gws_bytes, None, None, stream))
+            recon._check(lib.recon_solve(h, y.data_ptr(), B, prob.lam, prob.delta, iters, 0,
+                                         x.data_ptr(), 0, ws.data_ptr(), ws_bytes,
+                                         stats.data_ptr(), stream))
+            recon._check(lib.recon_forward(h, x.data_ptr(), B, yfit.data_ptr(), ws.data_ptr(),
+                                           ws_bytes, stream))
+        finally:
+            lib.recon_plan_destroy(h)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    recon.trace_enable(args.trace, capacity=args.steps * iters + 16)
+    times = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"step {i + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    kms = recon.trace_read()
+    recon.trace_enable(None)
+    st = recon.stats_to_numpy(stats, B)
+    ms_step = 1e3 * total / args.steps
+    value = B * args.steps / total
+
+    # roofline of the traced kernel
+    kb = kernel_bytes(args.trace, N, L, B)
+    avg_ms = float(np.mean(kms)) if len(kms) else float("nan")
+    achieved = kb / (avg_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=args.trace, achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None, avg_launch_ms=round(avg_ms, 5), launches=int(len(kms)),
+                    algorithmic_bytes_per_launch=kb)
+
+    # single-frame latency (one 256^2 reconstruction, same hot path, B = 1)
+    lat = []
+    y1 = y[:1].contiguous()
+    x1 = torch.empty((1, N, N), dtype=torch.complex64, device="cuda")
+    ws1, ws1_bytes = plan.workspace(1)
+    for i in range(args.latency_reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recon._check(lib.recon_solve(plan.handle, y1.data_ptr(), 1, prob.lam, prob.delta, iters,
+                                     0, x1.data_ptr(), 0, ws1.data_ptr(), ws1_bytes, None,
+                                     stream))
+        torch.cuda.synchronize()
+        if i:
+            lat.append(time.perf_counter() - t0)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "recons/sec",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 (fp64 Gram accumulation and reductions)",
+        "data": "synthetic",
+        "config": {"workload": f"256x256 spiral M={M} (16 interleaves, 2x angular "
+                               f"undersampling), hyperbolic delta={prob.delta}, "
+                               f"lambda={prob.lam}, {iters} iterations, batch of {B} frames "
+                               f"sharing the trajectory, L={L}",
+                   "global_batch": B, "image": N, "samples": M, "iters": iters,
+                   "parallelism": "none (1 GPU)"},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(times, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(times, 99)), 3),
+                       "what": f"one step = {B} reconstructions finishing together"},
+        "single_frame_latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                                    "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "roofline": roofline,
+        "status_ok_frames": int(np.sum(st["status"] == 0)),
+        "grad_ratio_median": float(np.median(st["grad_ratio"])),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle, one frame)")
+        cb, rel = cpu_baseline(args, torch, recon)
+        out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
+        out["rel_l2_vs_oracle_one_frame"] = rel
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

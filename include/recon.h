@@ -1,0 +1,228 @@
+/*
+ * recon.h - C ABI of the MI355X (gfx950) regularised spiral-MRI reconstruction.
+ *
+ * Method (Boubertakh, Giovannelli, De Cesare, Herment, "Regularized
+ * reconstruction of MR images from spiral acquisitions"):
+ *
+ *   minimise J(x) = ||y - A x||^2 + lambda * sum phi(|D x|)
+ *
+ *   A   exact non-uniform DFT of Section 2, Eq. ModDirect:
+ *         (A x)_l = (1/N) sum_{n,m} x[n][m] exp(+i 2 pi (kx_l m + ky_l n))
+ *   D   first-order pixel differences in both directions (Section 3.3,
+ *       Omega_1), non-periodic
+ *   phi hyperbolic sqrt(delta^2 + t^2) (edge preserving, convex), or the
+ *       paper's Huber function, or Hunt's quadratic
+ *
+ * The data term is evaluated in the image domain (Section 3.4, Eq. NewCritLS):
+ * b = A^H y (the paper's D, Eq. AnnMatGD) and the trajectory-only Gram kernel
+ * (the paper's G, Eq. DG) are computed once by exact sums; every iteration
+ * applies Q = A^H A as a zero-padded L x L FFT, a pointwise product with the
+ * real spectrum of the circulant-embedded kernel, an inverse FFT and a crop
+ * (the gradient 2 f*G - 2D of Appendix B).  The minimiser is the paper's
+ * pseudo-conjugate gradient with a Polak-Ribiere correction (Section 3.3),
+ * with a half-quadratic majorant step length.
+ *
+ * Conventions
+ *   - complex data are interleaved float pairs (re, im) ("complex64");
+ *   - an image is row-major [N][N]: row n pairs with k_y, column m with k_x;
+ *   - a batch of B frames is [B][N][N] (images) or [B][M] (samples);
+ *   - a trajectory is host float64 [M][2] = (k_x, k_y) in cycles/pixel with
+ *     |k_x|, |k_y| <= 0.5 (Section 2: F = [1, 1], k normalised to
+ *     [-0.5, 0.5]).
+ *
+ * Memory ownership
+ *   The library never allocates or frees device memory.  The caller provides
+ *   the plan memory (recon_plan_bytes), the solver workspace
+ *   (recon_workspace_bytes) and every input/output buffer; all device pointers
+ *   must be 256-byte aligned device allocations on the current device.
+ *   A plan handle is a small host object (recon_plan_destroy frees it, not
+ *   the caller's plan memory).
+ *
+ * Streams and errors
+ *   Every call enqueues work on `stream` (a hipStream_t, NULL = default
+ *   stream) and returns without synchronising.  Arguments are validated
+ *   before any launch; on error nothing is enqueued and a status != RECON_OK
+ *   is returned, with a detail string from recon_last_error() (per thread).
+ *   A plan is read-only after recon_gram_kernel and may be shared by several
+ *   streams; a workspace may only be used by one call at a time.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct recon_plan_s* recon_plan_t;
+
+typedef enum {
+  RECON_OK = 0,
+  RECON_E_ARG = 1,        /* null pointer, bad enum, negative count */
+  RECON_E_RANGE = 2,      /* N, L, M, k or a size outside the supported range */
+  RECON_E_NOMEM = 3,      /* caller buffer smaller than the *_bytes query */
+  RECON_E_HIP = 4,        /* HIP runtime error (detail in recon_last_error) */
+  RECON_E_STATE = 5,      /* call order violated (e.g. solve before gram) */
+  RECON_E_NONFINITE = 6   /* per-frame status: a NaN/Inf appeared */
+} recon_status_t;
+
+/* Operand precision of the NUDFT contractions (adjoint / forward). */
+typedef enum {
+  RECON_FP32 = 0,         /* FP32 operands, FP32 MFMA, FP32 accumulation */
+  RECON_BF16X3 = 1,       /* split bf16 hi+lo operands, 3 products, FP32 acc. */
+  RECON_FP16X3 = 2        /* split fp16 hi+lo operands, 3 products, FP32 acc. */
+} recon_prec_t;
+
+/* Penalty phi(s), s = |difference| (Section 3.3). */
+typedef enum {
+  RECON_PHI_HYPERBOLIC = 0,  /* sqrt(delta^2 + s^2) */
+  RECON_PHI_HUBER = 1,       /* s^2 if s <= delta else 2 delta s - delta^2 */
+  RECON_PHI_QUADRATIC = 2    /* s^2 (delta unused) */
+} recon_phi_t;
+
+/* Per-frame result of recon_solve, written to device memory. */
+typedef struct {
+  double J;            /* criterion at the returned x */
+  double grad_ratio;   /* ||grad J(x)|| / ||grad J(x0)|| */
+  double gnorm0;       /* ||grad J(x0)|| */
+  int32_t iters_done;  /* iterations run */
+  int32_t status;      /* RECON_OK or RECON_E_NONFINITE */
+} recon_stats_t;
+
+/* Supported ranges: 2 <= N <= 1024, L a power of two with 2N-1 <= L <= 2048,
+ * 64 <= L, 1 <= M <= 2^31-1, 1 <= B. */
+
+/* ---- sizes (host only, no device work) ---------------------------------- */
+
+/* Bytes of device memory a plan needs (trajectory, phasor tables for the
+ * NUDFT contractions, FFT twiddles, Gram spectrum).  0 on invalid sizes. */
+size_t recon_plan_bytes(int64_t M, int32_t N, int32_t L, int32_t prec);
+
+/* Bytes of scratch device memory recon_gram_kernel needs (split-K partial
+ * sums of the Gram kernel and the L x L embedding). */
+size_t recon_gram_workspace_bytes(int64_t M, int32_t N, int32_t L);
+
+/* Bytes of device workspace for recon_solve / recon_gram_apply /
+ * recon_adjoint / recon_forward on B frames of plan geometry (N, L, M). */
+size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B);
+
+/* ---- plan --------------------------------------------------------------- */
+
+/* Section 2: validates the trajectory (finite, |k| <= 0.5), copies it to the
+ * device and builds the FP32 (and, for split precisions, hi/lo) phasor
+ * tables exp(i 2 pi k j) of the separable NUDFT.  traj: host float64
+ * [M][2] (kx, ky).  L = 0 selects the smallest power of two >= 2N-1 (and
+ * >= 64).  plan_mem: device, >= recon_plan_bytes(M, N, L, prec); owned by
+ * the caller, must outlive the plan.  The tables are built asynchronously
+ * on `stream`; *out is valid on return. */
+recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L,
+                          int32_t prec, void* plan_mem, size_t plan_mem_bytes,
+                          void* stream, recon_plan_t* out);
+
+/* Geometry of a plan (any out pointer may be NULL). */
+recon_status_t recon_plan_info(recon_plan_t plan, int64_t* M, int32_t* N,
+                               int32_t* L, int32_t* prec);
+
+void recon_plan_destroy(recon_plan_t plan);
+
+/* Section 3.4 Eq. DG and Appendix A.1 Eq. AnnMatG: the trajectory-only
+ * kernel.  Computes the lag kernel h[a][b] = (1/N^2) sum_l
+ * exp(-i 2 pi (ky_l a + kx_l b)), a, b in [-(N-1), N-1] (h[a][b] is the
+ * paper's G[-b][-a]) with FP64 MFMA accumulation over all samples, embeds it
+ * circularly in L x L, takes its 2D FFT (FP32) and keeps the real spectrum
+ * inside the plan.  Must be called once before recon_solve /
+ * recon_gram_apply.  ws: device scratch >= recon_gram_workspace_bytes.
+ * Optional outputs (NULL to skip): khat_out device float32 [L][L] (p, q),
+ * the unscaled real spectrum; lag_out device complex128 [2N-1][2N-1]
+ * indexed [a + N-1][b + N-1]. */
+recon_status_t recon_gram_kernel(recon_plan_t plan, void* ws, size_t ws_bytes,
+                                 float* khat_out, double* lag_out,
+                                 void* stream);
+
+/* ---- operators ---------------------------------------------------------- */
+
+/* Appendix A.2, Eq. AnnMatGD: b[f] = A^H y[f], the paper's D
+ * ("DFT of the data"), as an MFMA contraction over the M samples.
+ * y: device complex64 [B][M]; b: device complex64 [B][N][N];
+ * yy_out: optional device float64 [B] receiving ||y[f]||^2.
+ * ws: device workspace >= recon_workspace_bytes(M, N, L, B). */
+recon_status_t recon_adjoint(recon_plan_t plan, const float* y, int32_t B,
+                             float* b, double* yy_out, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Section 2, Eq. ModDirect (noise-free): y[f] = A x[f] as an MFMA
+ * contraction.  x: device complex64 [B][N][N]; y: device complex64 [B][M]. */
+recon_status_t recon_forward(recon_plan_t plan, const float* x, int32_t B,
+                             float* y, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Section 3.4 / Appendix B: Qv[f] = A^H A v[f] by the zero-padded L x L FFT
+ * with the plan's Gram spectrum.  v, Qv: device complex64 [B][N][N]
+ * (may not alias).  Requires recon_gram_kernel. */
+recon_status_t recon_gram_apply(recon_plan_t plan, const float* v, int32_t B,
+                                float* Qv, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/* ---- solver ------------------------------------------------------------- */
+
+/* Section 3.3: minimise ||y - A x||^2 + lambda sum phi(|D x|) for B frames
+ * sharing the plan's trajectory, with `iters` iterations of the
+ * pseudo-conjugate gradient (Polak-Ribiere, PR+ with restart) and the
+ * half-quadratic majorant step, starting from x0 = 0 (x_in_is_x0 = 0) or from
+ * the contents of x (x_in_is_x0 = 1).  Computes b = A^H y itself.
+ * y: device complex64 [B][M]; x: device complex64 [B][N][N] (in/out);
+ * stats: optional device recon_stats_t [B].  Requires recon_gram_kernel.
+ * lambda >= 0, delta > 0 (ignored for the quadratic penalty), iters >= 0. */
+recon_status_t recon_solve(recon_plan_t plan, const float* y, int32_t B,
+                           float lambda, float delta, int32_t iters,
+                           int32_t phi, float* x, int32_t x_in_is_x0,
+                           void* ws, size_t ws_bytes, recon_stats_t* stats,
+                           void* stream);
+
+/* Resumable form of recon_solve for the same workspace (used to inspect the
+ * iteration state between iterations).
+ *   recon_solve_begin: b = A^H y (or b given: y == NULL and b_in != NULL),
+ *                      initial state from x0 (x0 == NULL means zeros);
+ *   recon_solve_iterate: run `iters` more iterations;
+ *   recon_solve_end:   objective and stats, copy x to x_out.
+ * recon_solve_export copies one state field of the current iterate to `out`
+ * (device complex64 [B][N][N]): 0 = x, 1 = r (= Q x - b), 2 = g (gradient),
+ * 3 = d (search direction for the next iteration), 4 = b. */
+recon_status_t recon_solve_begin(recon_plan_t plan, const float* y,
+                                 const float* b_in, int32_t B, float lambda,
+                                 float delta, int32_t phi, const float* x0,
+                                 void* ws, size_t ws_bytes, void* stream);
+recon_status_t recon_solve_iterate(recon_plan_t plan, int32_t iters, void* ws,
+                                   size_t ws_bytes, void* stream);
+recon_status_t recon_solve_end(recon_plan_t plan, float* x_out,
+                               recon_stats_t* stats, void* ws, size_t ws_bytes,
+                               void* stream);
+recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---- diagnostics -------------------------------------------------------- */
+
+/* Kernel timing trace (HIP events around every launch of one kernel kind on
+ * the launching stream).  kernel: -1 = off, 0 = direction + row FFT,
+ * 1 = column pass, 2 = inverse row FFT, 3 = CG update, 4 = adjoint
+ * contraction, 5 = Gram contraction, 6 = forward contraction.  capacity
+ * bounds the number of recorded launches (later ones are not recorded).
+ * Creating the events allocates no device buffers.  recon_trace_read waits
+ * for the recorded events and writes up to n durations (ms) to ms_out; it
+ * returns the number written, or -1 on error.  Tracing is process-wide and
+ * not thread-safe against concurrent solves. */
+recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity);
+int32_t recon_trace_read(float* ms_out, int32_t n);
+
+const char* recon_status_string(recon_status_t s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* recon_last_error(void);
+/* Library version string. */
+const char* recon_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RECON_H */

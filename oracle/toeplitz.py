@@ -12,9 +12,14 @@ L >= 2N - 1:
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft
 
 from . import nudft
+
+_WORKERS = os.cpu_count() or 1
 
 
 def apply_gram(v: np.ndarray, K: np.ndarray, N: int) -> np.ndarray:
@@ -23,7 +28,8 @@ def apply_gram(v: np.ndarray, K: np.ndarray, N: int) -> np.ndarray:
     v = np.asarray(v, dtype=np.complex128)
     pad = np.zeros(v.shape[:-2] + (L, L), dtype=np.complex128)
     pad[..., :N, :N] = v
-    out = np.fft.ifft2(K * np.fft.fft2(pad, axes=(-2, -1)), axes=(-2, -1))
+    out = scipy.fft.ifft2(K * scipy.fft.fft2(pad, axes=(-2, -1), workers=_WORKERS),
+                          axes=(-2, -1), workers=_WORKERS)
     return out[..., :N, :N].copy()
 
 

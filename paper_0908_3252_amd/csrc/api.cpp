@@ -1,0 +1,599 @@
+// C ABI of the reconstruction library: argument validation, memory layout of
+// the caller-owned plan and workspace buffers, and the enqueue order of the
+// kernels.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/recon.h"
+#include "kernels.hpp"
+
+using namespace recon;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+recon_status_t fail(recon_status_t s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+recon_status_t hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return RECON_E_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int default_L(int N) {
+  int L = 64;
+  while (L < 2 * N - 1) L *= 2;
+  return L;
+}
+
+recon_status_t check_geometry(int64_t M, int32_t N, int32_t L) {
+  if (N < 2 || N > 1024) return fail(RECON_E_RANGE, "N must be in [2, 1024]");
+  if (!is_pow2(L) || L < 64 || L > 2048)
+    return fail(RECON_E_RANGE, "L must be a power of two in [64, 2048]");
+  if (L < 2 * N - 1) return fail(RECON_E_RANGE, "L must be >= 2N-1");
+  if (M < 1 || M > (int64_t)0x7fffffff) return fail(RECON_E_RANGE, "M must be in [1, 2^31-1]");
+  return RECON_OK;
+}
+
+struct PlanLayout {
+  size_t k, ex, ey, tw, khat, total;
+};
+
+PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
+  (void)prec;
+  PlanLayout p{};
+  size_t off = 0;
+  p.k = off;
+  off = align_up(off + (size_t)M * 2 * sizeof(double));
+  p.ex = off;
+  off = align_up(off + (size_t)M * N * sizeof(float2));
+  p.ey = off;
+  off = align_up(off + (size_t)M * N * sizeof(float2));
+  p.tw = off;
+  off = align_up(off + (size_t)L * sizeof(float2));
+  p.khat = off;
+  off = align_up(off + (size_t)L * L * sizeof(float));
+  p.total = off;
+  return p;
+}
+
+struct WsLayout {
+  size_t b, x[2], r, g, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, adj, total;
+  int nb1, nb3, nb4, adj_splits;
+};
+
+WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
+  WsLayout w{};
+  const size_t img = (size_t)B * N * N * sizeof(float2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  w.b = take(img);
+  w.x[0] = take(img);
+  w.x[1] = take(img);
+  w.r = take(img);
+  w.g = take(img);
+  w.d[0] = take(img);
+  w.d[1] = take(img);
+  w.qd = take(img);
+  w.T = take((size_t)B * N * L * sizeof(float2));
+  w.nb1 = cdiv(N, fft_rows_per_block(L));
+  w.nb3 = w.nb1;
+  w.nb4 = cdiv(N, upd_rows_per_block(N));
+  w.p1 = take((size_t)B * w.nb1 * 2 * sizeof(double));
+  w.p3 = take((size_t)B * w.nb3 * sizeof(double));
+  w.p4 = take((size_t)B * w.nb4 * 4 * sizeof(double));
+  w.pg0 = take((size_t)B * w.nb4 * sizeof(double));
+  w.pobj = take((size_t)B * w.nb4 * 3 * sizeof(double));
+  w.params = take((size_t)B * sizeof(FrameParam));
+  w.yy = take((size_t)B * sizeof(double));
+  w.adj_splits = adjoint_splits(M, N);
+  {
+    const int g = adjoint_group(M, N);
+    const int frames = g < B ? g : B;
+    w.adj = take(w.adj_splits > 1 ? (size_t)w.adj_splits * frames * N * N * sizeof(float2) : 0);
+  }
+  w.total = off;
+  return w;
+}
+
+struct GramWsLayout {
+  size_t part, emb, emb2, total;
+  int splits;
+};
+
+GramWsLayout gram_ws_layout(int64_t M, int32_t N, int32_t L) {
+  GramWsLayout g{};
+  g.splits = gram_splits(M, N);
+  size_t off = 0;
+  g.part = off;
+  off = align_up(off + (size_t)g.splits * 4 * N * N * sizeof(double));
+  g.emb = off;
+  off = align_up(off + (size_t)L * L * sizeof(float2));
+  g.emb2 = off;
+  off = align_up(off + (size_t)L * L * sizeof(float2));
+  g.total = off;
+  return g;
+}
+
+// Event trace of one kernel kind (recon_trace_enable).
+struct Trace {
+  std::mutex mu;
+  int kernel = -1;
+  int capacity = 0;
+  int used = 0;
+  std::vector<hipEvent_t> ev;  // 2 per record
+} g_trace;
+
+struct TraceScope {
+  hipEvent_t stop = nullptr;
+  hipStream_t s;
+  TraceScope(int kernel, hipStream_t st) : s(st) {
+    if (g_trace.kernel != kernel) return;
+    std::lock_guard<std::mutex> lk(g_trace.mu);
+    if (g_trace.kernel != kernel || g_trace.used >= g_trace.capacity) return;
+    const int i = g_trace.used++;
+    (void)hipEventRecord(g_trace.ev[2 * i], s);
+    stop = g_trace.ev[2 * i + 1];
+  }
+  ~TraceScope() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+enum { TK_DIR = 0, TK_COL = 1, TK_ROWINV = 2, TK_UPDATE = 3, TK_ADJ = 4, TK_GRAM = 5, TK_FWD = 6 };
+
+struct SolveCtx {
+  int B = 0;
+  int phi = 0;
+  int iters = 0;
+  bool has_y = false;
+};
+
+}  // namespace
+
+struct recon_plan_s {
+  int64_t M;
+  int32_t N, L, prec;
+  char* mem;
+  size_t mem_bytes;
+  PlanLayout lay;
+  bool gram_done = false;
+  std::mutex mu;
+  std::unordered_map<void*, SolveCtx> solves;
+
+  double* k() const { return reinterpret_cast<double*>(mem + lay.k); }
+  float2* ex() const { return reinterpret_cast<float2*>(mem + lay.ex); }
+  float2* ey() const { return reinterpret_cast<float2*>(mem + lay.ey); }
+  float2* tw() const { return reinterpret_cast<float2*>(mem + lay.tw); }
+  float* khat() const { return reinterpret_cast<float*>(mem + lay.khat); }
+};
+
+namespace {
+
+struct Ws {
+  WsLayout lay;
+  char* base;
+  float2* img(size_t off) const { return reinterpret_cast<float2*>(base + off); }
+  double* dbl(size_t off) const { return reinterpret_cast<double*>(base + off); }
+  FrameParam* params() const { return reinterpret_cast<FrameParam*>(base + lay.params); }
+};
+
+recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws* out) {
+  if (!ws) return fail(RECON_E_ARG, "workspace is NULL");
+  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  out->lay = ws_layout(p->M, p->N, p->L, B);
+  if (ws_bytes < out->lay.total)
+    return fail(RECON_E_NOMEM, "workspace smaller than recon_workspace_bytes");
+  out->base = static_cast<char*>(ws);
+  return RECON_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Q v for B frames into out (T: N x L scratch per frame); optional <d, Qd> partials.
+recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, float2* T,
+                          const float2* d, double* p3, hipStream_t s) {
+  HIP_TRY(launch_rowfft_plain(p->L, p->N, B, v, T, p->tw(), s));
+  {
+    TraceScope ts(TK_COL, s);
+    HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat(), p->tw(), s));
+  }
+  {
+    TraceScope ts(TK_ROWINV, s);
+    HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, d, p3, p->tw(), s));
+  }
+  return RECON_OK;
+}
+
+recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b, float2* part,
+                              hipStream_t s) {
+  TraceScope ts(TK_ADJ, s);
+  HIP_TRY(launch_adjoint_f32(p->M, p->N, B, p->ex(), p->ey(), y, b, part, s));
+  return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t recon_plan_bytes(int64_t M, int32_t N, int32_t L, int32_t prec) {
+  if (L == 0) L = default_L(N);
+  if (check_geometry(M, N, L) != RECON_OK) return 0;
+  if (prec < 0 || prec > 2) return 0;
+  return plan_layout(M, N, L, prec).total;
+}
+
+size_t recon_gram_workspace_bytes(int64_t M, int32_t N, int32_t L) {
+  if (L == 0) L = default_L(N);
+  if (check_geometry(M, N, L) != RECON_OK) return 0;
+  return gram_ws_layout(M, N, L).total;
+}
+
+size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B) {
+  if (L == 0) L = default_L(N);
+  if (check_geometry(M, N, L) != RECON_OK || B < 1) return 0;
+  return ws_layout(M, N, L, B).total;
+}
+
+recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, int32_t prec,
+                          void* plan_mem, size_t plan_mem_bytes, void* stream,
+                          recon_plan_t* out) {
+  g_last_error.clear();
+  if (!traj || !plan_mem || !out) return fail(RECON_E_ARG, "NULL argument");
+  if (L == 0) L = default_L(N);
+  recon_status_t st = check_geometry(M, N, L);
+  if (st != RECON_OK) return st;
+  if (prec != RECON_FP32) {
+    if (prec == RECON_BF16X3 || prec == RECON_FP16X3)
+      return fail(RECON_E_RANGE, "split precisions are not available in this build");
+    return fail(RECON_E_ARG, "unknown precision");
+  }
+  for (int64_t i = 0; i < 2 * M; ++i) {
+    const double v = traj[i];
+    if (!std::isfinite(v) || std::fabs(v) > 0.5)
+      return fail(RECON_E_RANGE, "trajectory entries must be finite with |k| <= 0.5");
+  }
+  const PlanLayout lay = plan_layout(M, N, L, prec);
+  if (plan_mem_bytes < lay.total) return fail(RECON_E_NOMEM, "plan memory smaller than recon_plan_bytes");
+  auto* p = new recon_plan_s();
+  p->M = M;
+  p->N = N;
+  p->L = L;
+  p->prec = prec;
+  p->mem = static_cast<char*>(plan_mem);
+  p->mem_bytes = plan_mem_bytes;
+  p->lay = lay;
+  hipStream_t s = as_stream(stream);
+  std::vector<float2> tw(L);
+  for (int i = 0; i < L; ++i) {
+    const double a = -2.0 * M_PI * (double)i / (double)L;
+    tw[i] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  hipError_t e = hipMemcpyAsync(p->k(), traj, (size_t)M * 2 * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->tw(), tw.data(), (size_t)L * sizeof(float2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_tables_f32(M, N, p->k(), p->ex(), p->ey(), s);
+  // The host copies above read caller and local memory: finish before return.
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "recon_plan");
+  }
+  *out = p;
+  return RECON_OK;
+}
+
+recon_status_t recon_plan_info(recon_plan_t p, int64_t* M, int32_t* N, int32_t* L, int32_t* prec) {
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (M) *M = p->M;
+  if (N) *N = p->N;
+  if (L) *L = p->L;
+  if (prec) *prec = p->prec;
+  return RECON_OK;
+}
+
+void recon_plan_destroy(recon_plan_t p) { delete p; }
+
+recon_status_t recon_gram_kernel(recon_plan_t p, void* ws, size_t ws_bytes, float* khat_out,
+                                 double* lag_out, void* stream) {
+  g_last_error.clear();
+  if (!p || !ws) return fail(RECON_E_ARG, "NULL argument");
+  const GramWsLayout g = gram_ws_layout(p->M, p->N, p->L);
+  if (ws_bytes < g.total) return fail(RECON_E_NOMEM, "gram workspace smaller than recon_gram_workspace_bytes");
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  double* part = reinterpret_cast<double*>(base + g.part);
+  float2* emb = reinterpret_cast<float2*>(base + g.emb);
+  float2* emb2 = reinterpret_cast<float2*>(base + g.emb2);
+  {
+    TraceScope ts(TK_GRAM, s);
+    HIP_TRY(launch_gram_f64(p->M, p->N, p->k(), part, g.splits, s));
+  }
+  HIP_TRY(launch_gram_assemble(p->N, p->L, part, g.splits, lag_out, emb, s));
+  HIP_TRY(launch_rowfft_full(p->L, p->L, emb, p->tw(), s));
+  HIP_TRY(launch_transpose(p->L, emb, emb2, s));
+  HIP_TRY(launch_rowfft_full(p->L, p->L, emb2, p->tw(), s));
+  HIP_TRY(launch_khat_finish(p->L, emb2, p->khat(), khat_out, s));
+  p->gram_done = true;
+  return RECON_OK;
+}
+
+recon_status_t recon_adjoint(recon_plan_t p, const float* y, int32_t B, float* b, double* yy_out,
+                             void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p || !y || !b) return fail(RECON_E_ARG, "NULL argument");
+  Ws w;
+  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const float2* y2 = reinterpret_cast<const float2*>(y);
+  if (yy_out) HIP_TRY(launch_sumsq(p->M, B, y2, yy_out, s));
+  return adjoint_traced(p, y2, B, reinterpret_cast<float2*>(b), w.img(w.lay.adj), s);
+}
+
+recon_status_t recon_forward(recon_plan_t p, const float* x, int32_t B, float* y, void* ws,
+                             size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p || !x || !y) return fail(RECON_E_ARG, "NULL argument");
+  (void)ws;
+  (void)ws_bytes;
+  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  TraceScope ts(TK_FWD, as_stream(stream));
+  HIP_TRY(launch_forward_f32(p->M, p->N, B, p->ex(), p->ey(), reinterpret_cast<const float2*>(x),
+                             reinterpret_cast<float2*>(y), as_stream(stream)));
+  return RECON_OK;
+}
+
+recon_status_t recon_gram_apply(recon_plan_t p, const float* v, int32_t B, float* Qv, void* ws,
+                                size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p || !v || !Qv) return fail(RECON_E_ARG, "NULL argument");
+  if (v == Qv) return fail(RECON_E_ARG, "v and Qv may not alias");
+  if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
+  Ws w;
+  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st != RECON_OK) return st;
+  return gram_apply(p, reinterpret_cast<const float2*>(v), reinterpret_cast<float2*>(Qv), B,
+                    w.img(w.lay.T), nullptr, nullptr, as_stream(stream));
+}
+
+recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
+                                 float lambda, float delta, int32_t phi, const float* x0, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (!y && !b_in) return fail(RECON_E_ARG, "need y or b");
+  if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
+  if (phi < 0 || phi > 2) return fail(RECON_E_ARG, "unknown penalty");
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
+  if (phi != RECON_PHI_QUADRATIC && (!(delta > 0.f) || !std::isfinite(delta)))
+    return fail(RECON_E_RANGE, "delta must be > 0");
+  Ws w;
+  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const int N = p->N;
+  float2* b = w.img(w.lay.b);
+  double* yy = w.dbl(w.lay.yy);
+  if (y) {
+    const float2* y2 = reinterpret_cast<const float2*>(y);
+    HIP_TRY(launch_sumsq(p->M, B, y2, yy, s));
+    recon_status_t r = adjoint_traced(p, y2, B, b, w.img(w.lay.adj), s);
+    if (r != RECON_OK) return r;
+  } else {
+    HIP_TRY(hipMemcpyAsync(b, b_in, (size_t)B * N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_zero_f64((size_t)B, yy, s));
+  }
+  HIP_TRY(launch_set_params(B, lambda, delta, w.params(), s));
+  const float2* qx0 = nullptr;
+  if (x0) {
+    recon_status_t r = gram_apply(p, reinterpret_cast<const float2*>(x0), w.img(w.lay.qd), B,
+                                  w.img(w.lay.T), nullptr, nullptr, s);
+    if (r != RECON_OK) return r;
+    qx0 = w.img(w.lay.qd);
+  }
+  HIP_TRY(launch_init(phi, N, B, b, reinterpret_cast<const float2*>(x0), qx0, w.img(w.lay.x[0]),
+                      w.img(w.lay.r), w.img(w.lay.g), w.img(w.lay.d[0]), w.dbl(w.lay.p4),
+                      w.dbl(w.lay.pg0), w.params(), s));
+  std::lock_guard<std::mutex> lk(p->mu);
+  SolveCtx& c = p->solves[ws];
+  c.B = B;
+  c.phi = phi;
+  c.iters = 0;
+  c.has_y = y != nullptr;
+  return RECON_OK;
+}
+
+static recon_status_t get_ctx(recon_plan_t p, void* ws, SolveCtx* out) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  auto it = p->solves.find(ws);
+  if (it == p->solves.end()) return fail(RECON_E_STATE, "recon_solve_begin has not been called on this workspace");
+  *out = it->second;
+  return RECON_OK;
+}
+
+recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
+  SolveCtx c;
+  recon_status_t st = get_ctx(p, ws, &c);
+  if (st != RECON_OK) return st;
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const int N = p->N, L = p->L, B = c.B;
+  float2* T = w.img(w.lay.T);
+  for (int it = 0; it < iters; ++it) {
+    const int k = c.iters + it;
+    float2* d_old = w.img(w.lay.d[k & 1]);
+    float2* d_new = w.img(w.lay.d[(k + 1) & 1]);
+    float2* x_old = w.img(w.lay.x[k & 1]);
+    float2* x_new = w.img(w.lay.x[(k + 1) & 1]);
+    {
+      TraceScope ts(TK_DIR, s);
+      HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, w.img(w.lay.g), d_old, d_new, x_old, T,
+                                w.dbl(w.lay.p4), w.lay.nb4, w.dbl(w.lay.p1), w.params(), p->tw(),
+                                s));
+    }
+    {
+      TraceScope ts(TK_COL, s);
+      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), p->tw(), s));
+    }
+    {
+      TraceScope ts(TK_ROWINV, s);
+      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), d_new, w.dbl(w.lay.p3), p->tw(), s));
+    }
+    {
+      TraceScope ts(TK_UPDATE, s);
+      HIP_TRY(launch_update(c.phi, N, B, x_old, x_new, d_new, w.img(w.lay.r), w.img(w.lay.qd),
+                            w.img(w.lay.g), w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3),
+                            w.lay.nb3, w.dbl(w.lay.p4), w.params(), s));
+    }
+  }
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->solves[ws].iters = c.iters + iters;
+  return RECON_OK;
+}
+
+recon_status_t recon_solve_export(recon_plan_t p, int32_t field, float* out, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p || !out) return fail(RECON_E_ARG, "NULL argument");
+  SolveCtx c;
+  recon_status_t st = get_ctx(p, ws, &c);
+  if (st != RECON_OK) return st;
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const size_t bytes = (size_t)c.B * p->N * p->N * sizeof(float2);
+  const int k = c.iters;
+  float2* o = reinterpret_cast<float2*>(out);
+  switch (field) {
+    case 0: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.x[k & 1]), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 1: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.r), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 2: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.g), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 3:
+      HIP_TRY(launch_export_dir(p->N, c.B, w.img(w.lay.g), w.img(w.lay.d[k & 1]), o, w.dbl(w.lay.p4),
+                                w.lay.nb4, s));
+      break;
+    case 4: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.b), bytes, hipMemcpyDeviceToDevice, s)); break;
+    default: return fail(RECON_E_ARG, "unknown field");
+  }
+  return RECON_OK;
+}
+
+recon_status_t recon_solve_end(recon_plan_t p, float* x_out, recon_stats_t* stats, void* ws,
+                               size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  SolveCtx c;
+  recon_status_t st = get_ctx(p, ws, &c);
+  if (st != RECON_OK) return st;
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const int k = c.iters;
+  float2* x = w.img(w.lay.x[k & 1]);
+  if (stats) {
+    HIP_TRY(launch_objective(c.phi, p->N, c.B, x, w.img(w.lay.b), w.img(w.lay.r), w.dbl(w.lay.pobj),
+                             w.params(), s));
+    HIP_TRY(launch_stats(c.B, w.dbl(w.lay.pobj), w.lay.nb4, w.dbl(w.lay.p4), w.lay.nb4,
+                         w.dbl(w.lay.pg0), w.lay.nb4, w.dbl(w.lay.yy), k, w.params(), stats, s));
+  }
+  if (x_out && reinterpret_cast<float2*>(x_out) != x)
+    HIP_TRY(hipMemcpyAsync(x_out, x, (size_t)c.B * p->N * p->N * sizeof(float2),
+                           hipMemcpyDeviceToDevice, s));
+  return RECON_OK;
+}
+
+recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, float lambda, float delta,
+                           int32_t iters, int32_t phi, float* x, int32_t x_in_is_x0, void* ws,
+                           size_t ws_bytes, recon_stats_t* stats, void* stream) {
+  if (!p || !y || !x) return fail(RECON_E_ARG, "NULL argument");
+  if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
+  recon_status_t st = recon_solve_begin(p, y, nullptr, B, lambda, delta, phi,
+                                        x_in_is_x0 ? x : nullptr, ws, ws_bytes, stream);
+  if (st != RECON_OK) return st;
+  st = recon_solve_iterate(p, iters, ws, ws_bytes, stream);
+  if (st != RECON_OK) return st;
+  return recon_solve_end(p, x, stats, ws, ws_bytes, stream);
+}
+
+recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  for (hipEvent_t e : g_trace.ev) (void)hipEventDestroy(e);
+  g_trace.ev.clear();
+  g_trace.used = 0;
+  g_trace.kernel = -1;
+  g_trace.capacity = 0;
+  if (kernel < 0) return RECON_OK;
+  if (kernel > TK_FWD || capacity < 1) return fail(RECON_E_ARG, "bad trace request");
+  g_trace.ev.resize(2 * (size_t)capacity);
+  for (auto& e : g_trace.ev) HIP_TRY(hipEventCreate(&e));
+  g_trace.capacity = capacity;
+  g_trace.kernel = kernel;
+  return RECON_OK;
+}
+
+int32_t recon_trace_read(float* ms_out, int32_t n) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  if (!ms_out || n < 0) return -1;
+  const int m = g_trace.used < n ? g_trace.used : n;
+  for (int i = 0; i < m; ++i) {
+    if (hipEventSynchronize(g_trace.ev[2 * i + 1]) != hipSuccess) return -1;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_trace.ev[2 * i], g_trace.ev[2 * i + 1]) != hipSuccess) return -1;
+    ms_out[i] = ms;
+  }
+  return m;
+}
+
+const char* recon_status_string(recon_status_t s) {
+  switch (s) {
+    case RECON_OK: return "ok";
+    case RECON_E_ARG: return "invalid argument";
+    case RECON_E_RANGE: return "size or value out of range";
+    case RECON_E_NOMEM: return "buffer too small";
+    case RECON_E_HIP: return "HIP runtime error";
+    case RECON_E_STATE: return "call order violated";
+    case RECON_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* recon_last_error(void) { return g_last_error.c_str(); }
+
+const char* recon_version(void) { return "recon-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

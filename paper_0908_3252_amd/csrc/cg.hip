@@ -1,0 +1,303 @@
+// Pseudo-conjugate-gradient kernels (Section 3.3) around the Gram apply.
+//
+// One iteration (per frame, all frames of a batch in the same launches):
+//   dir+row pass : beta (PR+, restart) from the previous update's partials,
+//                  d = -g + beta d_old, partials Re<g,d>, sum w(|Dx|)|Dd|^2,
+//                  row FFTs of d                       (toeplitz.hip)
+//   column pass  : Gram spectrum product                (toeplitz.hip)
+//   row inverse  : Qd, partial Re<d, Qd>                (toeplitz.hip)
+//   update       : alpha = -Re<g,d> / (2 Re<d,Qd> + lam sum w|Dd|^2)
+//                  x += alpha d ; r += alpha Qd (r = Qx - b)
+//                  g = 2 r + lam D^T(w(|Dx|) Dx)  (gradient, Appendix B and
+//                  the penalty gradient), partials for beta   (this file)
+// All reductions are per-block FP64 partials summed in a fixed order by the
+// consumer kernel, so results do not depend on scheduling or batch size.
+// x and d are double-buffered because the stencils read neighbouring rows
+// that other blocks of the same launch overwrite.
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace recon {
+
+__global__ void k_zero_f64(size_t n, double* p) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void k_set_params(int B, float lam, float delta, FrameParam* fp) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < B) fp[f] = FrameParam{lam, delta};
+}
+
+// Rows n0-1 .. n0+ROWS of x (x_old + alpha d, or x as given) staged in LDS.
+template <int PHI>
+__global__ __launch_bounds__(256) void k_update(
+    int N, int ROWS, const float2* __restrict__ x_old, float2* __restrict__ x_new,
+    const float2* __restrict__ d, float2* __restrict__ r, const float2* __restrict__ qd,
+    float2* __restrict__ g, const double* __restrict__ p1, int nb1,
+    const double* __restrict__ p3, int nb3, double* __restrict__ p4,
+    const FrameParam* __restrict__ fp) {
+  extern __shared__ float2 xt[];  // [(ROWS+2)][N]
+  __shared__ double red[4 * 4];
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  // Step length: exact minimiser of the half-quadratic majorant along d.
+  const double* q1 = p1 + (size_t)f * nb1 * 2;
+  const double gd = wave_sum_partials(q1 + 0, nb1, 2);
+  const double cv = wave_sum_partials(q1 + 1, nb1, 2);
+  const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
+  const FrameParam prm = fp[f];
+  const double den = 2.0 * dqd + (double)prm.lam * cv;
+  const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
+  const float af = (float)alpha;
+
+  const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);  // [r_lo, r_hi)
+  for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const size_t idx = fo + (size_t)(r_lo + rr) * N + m;
+    const float2 xv = x_old[idx], dv = d[idx];
+    xt[(r_lo + rr - (n0 - 1)) * N + m] = make_float2(fmaf(af, dv.x, xv.x), fmaf(af, dv.y, xv.y));
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int own = min(ROWS, N - n0);
+  for (int i = threadIdx.x; i < own * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const int n = n0 + rr;
+    const size_t idx = fo + (size_t)n * N + m;
+    const float2* mid = xt + (rr + 1) * N;
+    const float2* up = (n > 0) ? mid - N : nullptr;
+    const float2* dn = (n + 1 < N) ? mid + N : nullptr;
+    const float2 div = divergence<PHI>(up, mid, dn, m, N, prm.delta);
+    const float2 rv = r[idx], qv = qd[idx], go = g[idx], dv = d[idx];
+    const float2 rn = make_float2(fmaf(af, qv.x, rv.x), fmaf(af, qv.y, rv.y));
+    const float2 gn = make_float2(fmaf(prm.lam, div.x, 2.f * rn.x), fmaf(prm.lam, div.y, 2.f * rn.y));
+    x_new[idx] = mid[m];
+    r[idx] = rn;
+    g[idx] = gn;
+    const double gx = gn.x, gy = gn.y;
+    acc[0] += gx * gx + gy * gy;
+    acc[1] += gx * (double)go.x + gy * (double)go.y;
+    acc[2] += gx * (double)dv.x + gy * (double)dv.y;
+    acc[3] += (double)go.x * (double)go.x + (double)go.y * (double)go.y;
+  }
+  block_sum<4>(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = p4 + ((size_t)f * gridDim.x + blockIdx.x) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = acc[k];
+  }
+}
+
+template <int PHI>
+__global__ __launch_bounds__(256) void k_init(
+    int N, int ROWS, const float2* __restrict__ b, const float2* __restrict__ x0,
+    const float2* __restrict__ qx0, float2* __restrict__ x, float2* __restrict__ r,
+    float2* __restrict__ g, float2* __restrict__ d, double* __restrict__ p4,
+    double* __restrict__ pg0, const FrameParam* __restrict__ fp) {
+  extern __shared__ float2 xt[];
+  __shared__ double red[1 * 4];
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  const FrameParam prm = fp[f];
+  const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);
+  for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const size_t idx = fo + (size_t)(r_lo + rr) * N + m;
+    xt[(r_lo + rr - (n0 - 1)) * N + m] = x0 ? x0[idx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  double acc[1] = {0.0};
+  const int own = min(ROWS, N - n0);
+  for (int i = threadIdx.x; i < own * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const int n = n0 + rr;
+    const size_t idx = fo + (size_t)n * N + m;
+    const float2* mid = xt + (rr + 1) * N;
+    const float2* up = (n > 0) ? mid - N : nullptr;
+    const float2* dn = (n + 1 < N) ? mid + N : nullptr;
+    const float2 div = divergence<PHI>(up, mid, dn, m, N, prm.delta);
+    const float2 bv = b[idx];
+    const float2 q = qx0 ? qx0[idx] : make_float2(0.f, 0.f);
+    const float2 rn = c_sub(q, bv);
+    const float2 gn = make_float2(fmaf(prm.lam, div.x, 2.f * rn.x), fmaf(prm.lam, div.y, 2.f * rn.y));
+    x[idx] = mid[m];
+    r[idx] = rn;
+    g[idx] = gn;
+    d[idx] = make_float2(0.f, 0.f);
+    acc[0] += (double)gn.x * (double)gn.x + (double)gn.y * (double)gn.y;
+  }
+  block_sum<1>(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = p4 + ((size_t)f * gridDim.x + blockIdx.x) * 4;
+    // |g|^2 with zero history: beta = 0, so the first direction is -g.
+    o[0] = acc[0];
+    o[1] = 0.0;
+    o[2] = 0.0;
+    o[3] = 0.0;
+    pg0[(size_t)f * gridDim.x + blockIdx.x] = acc[0];
+  }
+}
+
+// Criterion J = ||y||^2 - 2 Re<x, b> + Re<x, Qx> + lam sum phi(|Dx|)
+// (Section 3.4, Eq. NewCritLS) with Qx = r + b:
+// partials [Re<x, b>, Re<x, r>, sum phi] per block.
+template <int PHI>
+__global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const float2* __restrict__ x,
+                                                   const float2* __restrict__ b,
+                                                   const float2* __restrict__ r,
+                                                   double* __restrict__ pobj,
+                                                   const FrameParam* __restrict__ fp) {
+  __shared__ double red[3 * 4];
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  const double delta = fp[f].delta;
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int own = min(ROWS, N - n0);
+  for (int i = threadIdx.x; i < own * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const int n = n0 + rr;
+    const size_t idx = fo + (size_t)n * N + m;
+    const float2 xv = x[idx], bv = b[idx], rv = r[idx];
+    acc[0] += (double)xv.x * bv.x + (double)xv.y * bv.y;
+    acc[1] += (double)xv.x * rv.x + (double)xv.y * rv.y;
+    if (n + 1 < N) {
+      const float2 xd = x[idx + N];
+      const double tx = (double)xd.x - xv.x, ty = (double)xd.y - xv.y;
+      acc[2] += pen_phi<PHI>(tx * tx + ty * ty, delta);
+    }
+    if (m + 1 < N) {
+      const float2 xr = x[idx + 1];
+      const double tx = (double)xr.x - xv.x, ty = (double)xr.y - xv.y;
+      acc[2] += pen_phi<PHI>(tx * tx + ty * ty, delta);
+    }
+  }
+  block_sum<3>(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = pobj + ((size_t)f * gridDim.x + blockIdx.x) * 3;
+    o[0] = acc[0];
+    o[1] = acc[1];
+    o[2] = acc[2];
+  }
+}
+
+struct StatsOut {
+  double J, grad_ratio, gnorm0;
+  int32_t iters_done, status;
+};
+
+__global__ void k_stats(int B, const double* __restrict__ pobj, int nbo,
+                        const double* __restrict__ p4, int nb4,
+                        const double* __restrict__ pg0, int nbg,
+                        const double* __restrict__ yy, int iters,
+                        const FrameParam* __restrict__ fp, StatsOut* __restrict__ st) {
+  // one wavefront per frame
+  const int f = blockIdx.x;
+  if (f >= B) return;
+  const double xb = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 0, nbo, 3);
+  const double xr = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 1, nbo, 3);
+  const double ph = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 2, nbo, 3);
+  const double gg = wave_sum_partials(p4 + (size_t)f * nb4 * 4, nb4, 4);
+  const double g0 = wave_sum_partials(pg0 + (size_t)f * nbg, nbg, 1);
+  if (threadIdx.x == 0) {
+    const double J = yy[f] - xb + xr + (double)fp[f].lam * ph;
+    StatsOut o;
+    o.J = J;
+    o.gnorm0 = sqrt(g0);
+    o.grad_ratio = (g0 > 0.0) ? sqrt(gg / g0) : 0.0;
+    o.iters_done = iters;
+    o.status = (isfinite(J) && isfinite(gg)) ? 0 : 6;
+    st[f] = o;
+  }
+}
+
+__global__ void k_export_dir(int N, const float2* __restrict__ g, const float2* __restrict__ d_old,
+                             float2* __restrict__ out, const double* __restrict__ p4, int nb4) {
+  const int f = blockIdx.y;
+  const double* pf = p4 + (size_t)f * nb4 * 4;
+  const double gg = wave_sum_partials(pf + 0, nb4, 4);
+  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
+  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
+  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+  double beta = 0.0;
+  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
+  if (-gg + beta * gdo >= 0.0) beta = 0.0;
+  const float bf = (float)beta;
+  const size_t fo = (size_t)f * N * N;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)N * N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float2 gv = g[fo + i], dv = d_old[fo + i];
+    out[fo + i] = make_float2(fmaf(bf, dv.x, -gv.x), fmaf(bf, dv.y, -gv.y));
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define RECON_PHI_SWITCH(PHI_, CALL)                  \
+  switch (PHI_) {                                     \
+    case 0: { constexpr int PP = 0; CALL; } break;    \
+    case 1: { constexpr int PP = 1; CALL; } break;    \
+    case 2: { constexpr int PP = 2; CALL; } break;    \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s) {
+  k_zero_f64<<<(unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096), 256, 0, s>>>(n, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_params(int B, float lam, float delta, FrameParam* fp, hipStream_t s) {
+  k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int phi, int N, int B, const float2* x_old, float2* x_new,
+                         const float2* d, float2* r, const float2* qd, float2* g,
+                         const double* p1, int nb1, const double* p3, int nb3,
+                         double* p4, const FrameParam* fp, hipStream_t s) {
+  const int R = upd_rows_per_block(N);
+  dim3 grid(cdiv(N, R), B);
+  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
+  RECON_PHI_SWITCH(phi, (k_update<PP><<<grid, 256, shm, s>>>(N, R, x_old, x_new, d, r, qd, g,
+                                                             p1, nb1, p3, nb3, p4, fp)));
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int phi, int N, int B, const float2* b, const float2* x0,
+                       const float2* qx0, float2* x, float2* r, float2* g, float2* d,
+                       double* p4, double* pg0, const FrameParam* fp, hipStream_t s) {
+  const int R = upd_rows_per_block(N);
+  dim3 grid(cdiv(N, R), B);
+  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
+  RECON_PHI_SWITCH(phi, (k_init<PP><<<grid, 256, shm, s>>>(N, R, b, x0, qx0, x, r, g, d, p4,
+                                                           pg0, fp)));
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(int phi, int N, int B, const float2* x, const float2* b,
+                            const float2* r, double* pobj, const FrameParam* fp,
+                            hipStream_t s) {
+  const int R = upd_rows_per_block(N);
+  dim3 grid(cdiv(N, R), B);
+  RECON_PHI_SWITCH(phi, (k_objective<PP><<<grid, 256, 0, s>>>(N, R, x, b, r, pobj, fp)));
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4, int nb4,
+                         const double* pg0, int nbg, const double* yy, int iters,
+                         const FrameParam* fp, void* stats, hipStream_t s) {
+  k_stats<<<B, 64, 0, s>>>(B, pobj, nbo, p4, nb4, pg0, nbg, yy, iters, fp,
+                           reinterpret_cast<StatsOut*>(stats));
+  return hipGetLastError();
+}
+
+hipError_t launch_export_dir(int N, int B, const float2* g, const float2* d_old, float2* out,
+                             const double* p4, int nb4, hipStream_t s) {
+  dim3 grid(cdiv(N * N, 256 * 4), B);
+  k_export_dir<<<grid, 256, 0, s>>>(N, g, d_old, out, p4, nb4);
+  return hipGetLastError();
+}
+
+}  // namespace recon

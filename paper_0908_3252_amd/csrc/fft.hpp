@@ -1,0 +1,186 @@
+// Stockham FFT of power-of-two length L held in registers by a team of
+// T = L/8 threads (8 values per thread), with LDS exchanges between passes.
+//
+// Layout: on entry thread t of the team holds v[e] = X[t + e*T], e = 0..7;
+// on exit it holds v[e] = Xhat[t + e*T] in the same strided layout, so both
+// the first pass's loads and the last pass's stores are unit-stride across
+// the team (coalesced in global memory, conflict-free in LDS).
+//
+// Passes (self-sorting Stockham, decimation in time): one leading radix-2 or
+// radix-4 pass when log2(L) is not a multiple of 3, then radix-8 passes.  A
+// pass of radix R over span Ns treats butterfly j = t + u*T (u < 8/R) with
+// inputs X[j + r*L/R] = v[u + r*(8/R)], twiddles W_{Ns R}^{r k} (k = j mod
+// Ns), an R-point DFT, and outputs at (j - k) R + k + r Ns.
+//
+// Pruning for the zero-padded Gram apply: HALF_IN declares X[i] = 0 for
+// i >= L/2 (v[4..7] = 0 on entry, folded out of the first pass); a caller
+// that only needs outputs i < L/2 reads only v[0..3], and the compiler drops
+// the unused half of the last pass.
+//
+// Forward transform: Xhat[p] = sum_i X[i] exp(-2 pi i p / L); inverse: the
+// conjugate kernel, unnormalised.
+#pragma once
+#include "common.hpp"
+
+namespace recon {
+
+template <int L>
+struct FftShape {
+  static constexpr int LOG = (L == 64) ? 6 : (L == 128) ? 7 : (L == 256) ? 8
+                            : (L == 512) ? 9 : (L == 1024) ? 10 : (L == 2048) ? 11 : -1;
+  static_assert(LOG > 0, "unsupported FFT length");
+  static constexpr int T = L / 8;
+  static constexpr int NR8 = LOG / 3;
+  static constexpr int REM = LOG % 3;
+  static constexpr int NP = NR8 + (REM ? 1 : 0);
+  static constexpr int PAD = L + L / 8;  // padded LDS entries per buffer
+};
+
+// LDS index padding: one spare slot every 8 entries breaks the stride-8
+// write pattern of the first passes across banks.
+__device__ __forceinline__ int lpad(int p) { return p + (p >> 3); }
+
+template <bool INV>
+__device__ __forceinline__ float2 mul_w4(float2 a) {  // a * exp(-+ 2 pi i / 4)
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8(float2 a) {  // a * exp(-+ 2 pi i / 8)
+  const float s = 0.70710678118654752440f;
+  return INV ? make_float2((a.x - a.y) * s, (a.x + a.y) * s)
+             : make_float2((a.x + a.y) * s, (a.y - a.x) * s);
+}
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8_3(float2 a) {  // a * exp(-+ 2 pi i 3 / 8)
+  const float s = 0.70710678118654752440f;
+  return INV ? make_float2((-a.x - a.y) * s, (a.x - a.y) * s)
+             : make_float2((a.y - a.x) * s, (-a.x - a.y) * s);
+}
+
+// In-place R-point DFTs, natural order in and out.  HALF: a[R/2..R-1] = 0.
+template <bool INV, bool HALF>
+__device__ __forceinline__ void dft2(float2* a) {
+  if (HALF) {
+    a[1] = a[0];
+  } else {
+    const float2 t = a[0];
+    a[0] = c_add(t, a[1]);
+    a[1] = c_sub(t, a[1]);
+  }
+}
+
+template <bool INV, bool HALF>
+__device__ __forceinline__ void dft4(float2* a) {
+  if (HALF) {
+    const float2 w = mul_w4<INV>(a[1]);
+    const float2 a0 = a[0], a1 = a[1];
+    a[0] = c_add(a0, a1);
+    a[2] = c_sub(a0, a1);
+    a[1] = c_add(a0, w);
+    a[3] = c_sub(a0, w);
+  } else {
+    const float2 s02 = c_add(a[0], a[2]), d02 = c_sub(a[0], a[2]);
+    const float2 s13 = c_add(a[1], a[3]), d13 = mul_w4<INV>(c_sub(a[1], a[3]));
+    a[0] = c_add(s02, s13);
+    a[2] = c_sub(s02, s13);
+    a[1] = c_add(d02, d13);
+    a[3] = c_sub(d02, d13);
+  }
+}
+
+template <bool INV, bool HALF>
+__device__ __forceinline__ void dft8(float2* a) {
+  float2 e[4] = {a[0], a[2], a[4], a[6]};
+  float2 o[4] = {a[1], a[3], a[5], a[7]};
+  dft4<INV, HALF>(e);
+  dft4<INV, HALF>(o);
+  o[1] = mul_w8<INV>(o[1]);
+  o[2] = mul_w4<INV>(o[2]);
+  o[3] = mul_w8_3<INV>(o[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = c_add(e[k], o[k]);
+    a[k + 4] = c_sub(e[k], o[k]);
+  }
+}
+
+template <int R, bool INV, bool HALF>
+__device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2<INV, HALF>(a);
+  else if constexpr (R == 4) dft4<INV, HALF>(a);
+  else dft8<INV, HALF>(a);
+}
+
+// One Stockham pass; returns the output positions of v[e] in pos[e].
+template <int L, int R, int NS, bool INV, bool HALF>
+__device__ __forceinline__ void fft_pass(float2 (&v)[8], int t, const float2* tw,
+                                         int (&pos)[8]) {
+  constexpr int NB = 8 / R;
+  constexpr int T = L / 8;
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int j = t + u * T;
+    const int k = j & (NS - 1);
+    float2 a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
+    if constexpr (NS > 1) {
+      constexpr int STEP = L / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * STEP];
+        if (INV) w.y = -w.y;
+        a[r] = c_mul(a[r], w);
+      }
+    }
+    dft<R, INV, HALF>(a);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v[u + r * NB] = a[r];
+      pos[u + r * NB] = base + r * NS;
+    }
+  }
+}
+
+template <int L, bool INV, bool HALF_IN, int P, int NS>
+__device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
+                                           float2* buf1, const float2* tw) {
+  using S = FftShape<L>;
+  constexpr int R = (P == 0 && S::REM) ? (1 << S::REM) : 8;
+  constexpr bool HALF = HALF_IN && (P == 0);
+  int pos[8];
+  fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
+  if constexpr (P + 1 < S::NP) {
+    float2* buf = (P & 1) ? buf1 : buf0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = buf[lpad(t + e * S::T)];
+    fft_passes<L, INV, HALF_IN, P + 1, NS * R>(v, t, buf0, buf1, tw);
+  }
+  // Last pass: j < L/R = NS, so pos[e] = t + e*T and v is already in the
+  // strided output layout.
+}
+
+// Full transform.  Every thread of the block must call this (it contains
+// block barriers).  buf0/buf1: this team's two LDS buffers of PAD entries;
+// tw: LDS table tw[i] = exp(-2 pi i i / L), i < L.
+template <int L, bool INV, bool HALF_IN>
+__device__ __forceinline__ void fft_team(float2 (&v)[8], int t, float2* buf0,
+                                         float2* buf1, const float2* tw) {
+  if (HALF_IN) {
+#pragma unroll
+    for (int e = 4; e < 8; ++e) v[e] = make_float2(0.f, 0.f);
+  }
+  fft_passes<L, INV, HALF_IN, 0, 1>(v, t, buf0, buf1, tw);
+}
+
+// Copy the plan's twiddle table (global) into LDS.
+template <int L>
+__device__ __forceinline__ void load_twiddles(float2* tw, const float2* __restrict__ g) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = g[i];
+}
+
+}  // namespace recon

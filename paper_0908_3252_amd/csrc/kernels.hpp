@@ -1,0 +1,123 @@
+// Host-side launchers of the HIP kernels (defined in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace recon {
+
+// Per-frame penalty parameters (device array, one entry per frame).
+struct FrameParam {
+  float lam;
+  float delta;
+};
+
+// Rows handled by one 256-thread block of the row-FFT kernels.
+inline int fft_rows_per_block(int L) { return 2048 / L; }
+// Columns handled by one block of the column kernel.
+inline int fft_cols_per_block(int L) { return L <= 64 ? 32 : (L <= 512 ? 16 : 8); }
+// Rows per block of the elementwise update kernel.
+inline int upd_rows_per_block(int N) { return N >= 256 ? 2 : (N >= 64 ? 4 : 8); }
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---- Gram apply (Section 3.4) ------------------------------------------------
+// Row pass: T[f][n][:] = FFT_L(zero-padded v[f][n][:]) for n < N.
+hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
+                               const float2* tw, hipStream_t s);
+// Column pass (in place): column q of T[f] -> IFFT_L(khat_s[q][:] * FFT_L(col)),
+// rows n < N kept.  khat_s is the transposed spectrum scaled by 1/L^2.
+hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s,
+                          const float2* tw, hipStream_t s);
+// Row inverse pass: out[f][n][m] = IFFT_L(T[f][n][:])[m] for m < N.  With
+// d != NULL also writes per-block partials Re<d, out> to p3[f][blk].
+hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
+                          const float2* d, double* p3, const float2* tw,
+                          hipStream_t s);
+
+// Full-length transforms for the spectrum build: rows of an [rows][L]
+// complex array in place, forward.
+hipError_t launch_rowfft_full(int L, int rows, float2* data, const float2* tw,
+                              hipStream_t s);
+
+// ---- CG kernels (Section 3.3) -------------------------------------------------
+// Direction update d_new = -g + beta d_old (beta from the update partials,
+// PR+ with restart), partials Re<g, d_new> and sum w(x)|D d_new|^2, and the
+// row pass of the Gram apply on d_new.
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
+                             const float2* d_old, float2* d_new,
+                             const float2* x, float2* T, const double* p4,
+                             int nb4, double* p1, const FrameParam* fp,
+                             const float2* tw, hipStream_t s);
+// alpha from the partials; x_new = x + alpha d, r += alpha Qd,
+// g = 2 r + lam D^T(w(D x_new) D x_new); partials for beta.
+hipError_t launch_update(int phi, int N, int B, const float2* x_old,
+                         float2* x_new, const float2* d, float2* r,
+                         const float2* qd, float2* g, const double* p1,
+                         int nb1, const double* p3, int nb3, double* p4,
+                         const FrameParam* fp, hipStream_t s);
+// Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), g = 2r +
+// grad R(x0), d = 0; partials such that the first direction is -g.
+hipError_t launch_init(int phi, int N, int B, const float2* b,
+                       const float2* x0, const float2* qx0, float2* x,
+                       float2* r, float2* g, float2* d, double* p4,
+                       double* pg0, const FrameParam* fp, hipStream_t s);
+hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s);
+hipError_t launch_set_params(int B, float lam, float delta, FrameParam* fp,
+                             hipStream_t s);
+// Objective partials and final statistics.
+hipError_t launch_objective(int phi, int N, int B, const float2* x,
+                            const float2* b, const float2* r, double* pobj,
+                            const FrameParam* fp, hipStream_t s);
+hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4,
+                        int nb4, const double* pg0, int nbg, const double* yy,
+                        int iters, const FrameParam* fp, void* stats,
+                        hipStream_t s);
+// Materialise the pending direction -g + beta d_old (as the next direction
+// kernel would) into out.
+hipError_t launch_export_dir(int N, int B, const float2* g, const float2* d_old,
+                             float2* out, const double* p4, int nb4,
+                             hipStream_t s);
+
+// ---- NUDFT (Section 2, Appendix A.2) -------------------------------------------
+// Phasor tables E[l][j] = exp(i 2 pi k_l j), j < N, FP32 complex, for both
+// axes: ex from k_x, ey from k_y.  k: device float64 [M][2].
+hipError_t launch_tables_f32(int64_t M, int N, const double* k, float2* ex,
+                             float2* ey, hipStream_t s);
+// Split-precision tables: hi = round(E), lo = round(E - hi) in bf16 (prec 1)
+// or fp16 (prec 2), planes [M][N] of (re, im) pairs.
+hipError_t launch_tables_split(int prec, int64_t M, int N, const float2* ex,
+                               const float2* ey, void* ex_hi, void* ex_lo,
+                               void* ey_hi, void* ey_lo, hipStream_t s);
+// Adjoint: b[f][n][m] = (1/N) sum_l conj(ey[l][n]) y[f][l] conj(ex[l][m]).
+// Split-K over `splits` sample ranges into part[s][f][n][m] when splits > 1.
+int adjoint_splits(int64_t M, int N);
+int adjoint_group(int64_t M, int N);
+hipError_t launch_adjoint_f32(int64_t M, int N, int B, const float2* ex,
+                              const float2* ey, const float2* y, float2* b,
+                              float2* part, hipStream_t s);
+hipError_t launch_forward_f32(int64_t M, int N, int B, const float2* ex,
+                              const float2* ey, const float2* x, float2* y,
+                              hipStream_t s);
+hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* yy,
+                        hipStream_t s);
+
+// ---- Gram kernel (Eq. DG, FP64) ----------------------------------------------
+int gram_splits(int64_t M, int N);
+// Four real products over the samples of split s:
+// part[s][0..3][a][b] = sum_l (Yr Xr, Yi Xi, Yr Xi, Yi Xr) with
+// Y = exp(-i 2 pi ky a), X = exp(-i 2 pi kx b), a, b < N.
+hipError_t launch_gram_f64(int64_t M, int N, const double* k, double* part,
+                           int splits, hipStream_t s);
+// Reduce the split partials, scale by 1/N^2, assemble h over the full lag
+// range (conjugate symmetry), optionally export it (lag_out complex128
+// [2N-1][2N-1]) and embed it circularly into emb [L][L] (FP32 complex).
+hipError_t launch_gram_assemble(int N, int L, const double* part, int splits,
+                                double* lag_out, float2* emb, hipStream_t s);
+// Transpose an [L][L] complex array (out[q][p] = in[p][q]).
+hipError_t launch_transpose(int L, const float2* in, float2* out, hipStream_t s);
+// khat_s[q][p] = Re(spec_t[q][p]) / L^2 ; khat_out[p][q] = Re(spec_t[q][p]).
+hipError_t launch_khat_finish(int L, const float2* spec_t, float* khat_s,
+                              float* khat_out, hipStream_t s);
+
+}  // namespace recon

@@ -1,0 +1,60 @@
+// Edge-preserving penalty on first-order pixel differences (Section 3.3).
+//
+// phi acts on the modulus s = |t| of each complex difference t; the
+// gradient and the half-quadratic majorant use the weight w(s) = phi'(s)/s:
+//   PHI 0  hyperbolic  phi = sqrt(delta^2 + s^2)     w = 1/sqrt(delta^2 + s^2)
+//   PHI 1  Huber       phi = s^2 (s <= delta), 2 delta s - delta^2 otherwise
+//                      w = 2 (s <= delta), 2 delta / s otherwise
+//   PHI 2  quadratic   phi = s^2                     w = 2
+#pragma once
+#include "common.hpp"
+
+namespace recon {
+
+template <int PHI>
+__device__ __forceinline__ float pen_weight(float s2, float delta) {
+  if constexpr (PHI == 0) {
+    return rsqrtf(fmaf(delta, delta, s2));
+  } else if constexpr (PHI == 1) {
+    return (s2 <= delta * delta) ? 2.f : 2.f * delta * rsqrtf(s2);
+  } else {
+    return 2.f;
+  }
+}
+
+template <int PHI>
+__device__ __forceinline__ double pen_phi(double s2, double delta) {
+  if constexpr (PHI == 0) {
+    return sqrt(delta * delta + s2);
+  } else if constexpr (PHI == 1) {
+    return (s2 <= delta * delta) ? s2 : 2.0 * delta * sqrt(s2) - delta * delta;
+  } else {
+    return s2;
+  }
+}
+
+// w(|t|) t for the difference t = b - a.
+template <int PHI>
+__device__ __forceinline__ float2 wdiff(float2 a, float2 b, float delta) {
+  const float2 t = c_sub(b, a);
+  return c_scale(t, pen_weight<PHI>(c_abs2(t), delta));
+}
+
+// (D^T (w . D x))[n][m] from a tile holding rows n-1, n, n+1 of x:
+// up/mid/dn point at column 0 of those rows (up/dn may be null at the image
+// border).  Vertical differences exist for rows 0..N-2, horizontal for
+// columns 0..N-2 (non-periodic).
+template <int PHI>
+__device__ __forceinline__ float2 divergence(const float2* up, const float2* mid,
+                                             const float2* dn, int m, int N,
+                                             float delta) {
+  const float2 c = mid[m];
+  float2 acc = make_float2(0.f, 0.f);
+  if (up) acc = c_add(acc, wdiff<PHI>(up[m], c, delta));
+  if (dn) acc = c_sub(acc, wdiff<PHI>(c, dn[m], delta));
+  if (m > 0) acc = c_add(acc, wdiff<PHI>(mid[m - 1], c, delta));
+  if (m + 1 < N) acc = c_sub(acc, wdiff<PHI>(c, mid[m + 1], delta));
+  return acc;
+}
+
+}  // namespace recon

@@ -1,0 +1,334 @@
+// Gram operator Q = A^H A applied in the image domain (Section 3.4 and
+// Appendix B): the data-term gradient is a linear 2D correlation of the
+// image with the trajectory-only kernel, evaluated exactly as
+//
+//   Q v = crop_N( IFFT_L( khat * FFT_L( pad_L(v) ) ) ),   L >= 2N - 1,
+//
+// in three streaming passes over an N x L intermediate (only the N non-zero
+// rows of the padded image are transformed along rows, and only the N kept
+// rows are produced along columns):
+//   row pass      v[N][N]  -> T[N][L]      (row FFTs, first half of inputs zero)
+//   column pass   T[N][L]  -> T[N][L]      (column FFT, x khat, column IFFT,
+//                                           in place, tiles staged in LDS)
+//   row inverse   T[N][L]  -> Qv[N][N]     (row IFFTs, first N outputs kept)
+// The direction update of the conjugate gradient (and its step-length
+// partials) is fused into the row pass; the <d, Qd> partial into the
+// inverse row pass.
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace recon {
+
+// ----------------------------------------------------------------- row pass
+template <int L>
+__global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __restrict__ v,
+                                                      float2* __restrict__ T,
+                                                      const float2* __restrict__ twg) {
+  using S = FftShape<L>;
+  constexpr int ROWS = 256 / S::T;
+  __shared__ float2 tw[L];
+  __shared__ float2 bufs[ROWS][2][S::PAD];
+  const int f = blockIdx.y;
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  const int n = blockIdx.x * ROWS + team;
+  load_twiddles<L>(tw, twg);
+  float2 val[8];
+  const float2* row = v + ((size_t)f * N + n) * N;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int p = t + e * S::T;
+    val[e] = (n < N && p < N) ? row[p] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_team<L, false, true>(val, t, bufs[team][0], bufs[team][1], tw);
+  if (n < N) {
+    float2* out = T + ((size_t)f * N + n) * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[t + e * S::T] = val[e];
+  }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_rowfft_full(int rows, float2* __restrict__ data,
+                                                     const float2* __restrict__ twg) {
+  using S = FftShape<L>;
+  constexpr int ROWS = 256 / S::T;
+  __shared__ float2 tw[L];
+  __shared__ float2 bufs[ROWS][2][S::PAD];
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  const int n = blockIdx.x * ROWS + team;
+  load_twiddles<L>(tw, twg);
+  float2 val[8];
+  float2* row = data + (size_t)n * L;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) val[e] = (n < rows) ? row[t + e * S::T] : make_float2(0.f, 0.f);
+  __syncthreads();
+  fft_team<L, false, false>(val, t, bufs[team][0], bufs[team][1], tw);
+  if (n < rows) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) row[t + e * S::T] = val[e];
+  }
+}
+
+// --------------------------------------------- CG direction + row pass (fused)
+// Block = ROWS image rows of frame f.  Phase A builds d_new = -g + beta d_old
+// for the block's rows plus one halo row below (recomputed bit-identically
+// by the owner block) in LDS, together with x; phase B forms the partials
+// Re<g, d_new> and sum w(|D x|) |D d_new|^2; phase C transforms the rows.
+template <int L, int PHI>
+__global__ __launch_bounds__(256) void k_dir_rowfft(
+    int N, const float2* __restrict__ g, const float2* __restrict__ d_old,
+    float2* __restrict__ d_new, const float2* __restrict__ x, float2* __restrict__ T,
+    const double* __restrict__ p4, int nb4, double* __restrict__ p1,
+    const FrameParam* __restrict__ fp, const float2* __restrict__ twg) {
+  using S = FftShape<L>;
+  constexpr int ROWS = 256 / S::T;
+  constexpr int TILE = (ROWS + 1) * (L / 2);
+  constexpr int FFTB = ROWS * 2 * S::PAD;
+  constexpr int SH = (2 * TILE > FFTB) ? 2 * TILE : FFTB;
+  __shared__ float2 tw[L];
+  __shared__ float2 sh[SH];
+  __shared__ double red[2 * 4];
+  float2* Dt = sh;          // [ROWS+1][N] d_new (phase A/B), aliased by FFT buffers
+  float2* Xt = sh + TILE;   // [ROWS+1][N] x
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  load_twiddles<L>(tw, twg);
+
+  // beta of the Polak-Ribiere (PR+) correction, with restart, from the
+  // update kernel's partials: [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
+  const double* pf = p4 + (size_t)f * nb4 * 4;
+  const double gg = wave_sum_partials(pf + 0, nb4, 4);
+  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
+  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
+  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+  double beta = 0.0;
+  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
+  if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
+  const float bf = (float)beta;
+
+  // Phase A
+  const int nrows = min(ROWS + 1, N - n0);
+  double gd = 0.0;
+  for (int i = threadIdx.x; i < nrows * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const size_t idx = fo + (size_t)(n0 + rr) * N + m;
+    const float2 gv = g[idx], dv = d_old[idx];
+    const float2 dn = make_float2(fmaf(bf, dv.x, -gv.x), fmaf(bf, dv.y, -gv.y));
+    Dt[rr * N + m] = dn;
+    Xt[rr * N + m] = x[idx];
+    if (rr < ROWS) {
+      d_new[idx] = dn;
+      gd += (double)gv.x * (double)dn.x + (double)gv.y * (double)dn.y;
+    }
+  }
+  __syncthreads();
+  // Phase B: curvature of the half-quadratic majorant along d_new.
+  const float delta = fp[f].delta;
+  double cv = 0.0;
+  const int own = min(ROWS, N - n0);
+  for (int i = threadIdx.x; i < own * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const int n = n0 + rr;
+    const float2 x0 = Xt[rr * N + m], e0 = Dt[rr * N + m];
+    if (n + 1 < N) {
+      const float2 tx = c_sub(Xt[(rr + 1) * N + m], x0);
+      const float2 te = c_sub(Dt[(rr + 1) * N + m], e0);
+      cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+    }
+    if (m + 1 < N) {
+      const float2 tx = c_sub(Xt[rr * N + m + 1], x0);
+      const float2 te = c_sub(Dt[rr * N + m + 1], e0);
+      cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+    }
+  }
+  // Phase C: row FFTs of d_new.
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  const int n = n0 + team;
+  float2 val[8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int p = t + e * S::T;
+    val[e] = (n < N && p < N) ? Dt[team * N + p] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();  // LDS tiles are reused as FFT buffers below
+  float2* b0 = sh + team * 2 * S::PAD;
+  fft_team<L, false, true>(val, t, b0, b0 + S::PAD, tw);
+  if (n < N) {
+    float2* out = T + ((size_t)f * N + n) * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[t + e * S::T] = val[e];
+  }
+  double v2[2] = {gd, cv};
+  block_sum<2>(v2, red);
+  if (threadIdx.x == 0) {
+    double* o = p1 + ((size_t)f * gridDim.x + blockIdx.x) * 2;
+    o[0] = v2[0];
+    o[1] = v2[1];
+  }
+}
+
+// ---------------------------------------------------------------- column pass
+template <int L, int COLS>
+__global__ __launch_bounds__(256) void k_colpass(int N, float2* __restrict__ T,
+                                                 const float* __restrict__ khat_s,
+                                                 const float2* __restrict__ twg) {
+  using S = FftShape<L>;
+  constexpr int TEAMS = 256 / S::T;
+  static_assert(COLS % TEAMS == 0, "columns per block must be a multiple of teams");
+  __shared__ float2 tw[L];
+  __shared__ float2 tile[(L / 2) * COLS];
+  __shared__ float2 bufs[TEAMS][2][S::PAD];
+  const int f = blockIdx.y;
+  const int q0 = blockIdx.x * COLS;
+  float2* Tf = T + (size_t)f * N * L;
+  load_twiddles<L>(tw, twg);
+  for (int i = threadIdx.x; i < N * COLS; i += 256) {
+    const int n = i / COLS, c = i - n * COLS;
+    tile[i] = Tf[(size_t)n * L + q0 + c];
+  }
+  __syncthreads();
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+#pragma unroll 1
+  for (int c0 = 0; c0 < COLS; c0 += TEAMS) {
+    const int c = c0 + team;
+    float2 val[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int p = t + e * S::T;
+      val[e] = (p < N) ? tile[p * COLS + c] : make_float2(0.f, 0.f);
+    }
+    fft_team<L, false, true>(val, t, bufs[team][0], bufs[team][1], tw);
+    const float* kq = khat_s + (size_t)(q0 + c) * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) val[e] = c_scale(val[e], kq[t + e * S::T]);
+    __syncthreads();
+    fft_team<L, true, false>(val, t, bufs[team][0], bufs[team][1], tw);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int p = t + e * S::T;
+      if (p < N) tile[p * COLS + c] = val[e];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < N * COLS; i += 256) {
+    const int n = i / COLS, c = i - n * COLS;
+    Tf[(size_t)n * L + q0 + c] = tile[i];
+  }
+}
+
+// --------------------------------------------------------- row inverse pass
+template <int L>
+__global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict__ T,
+                                                 float2* __restrict__ out,
+                                                 const float2* __restrict__ d,
+                                                 double* __restrict__ p3,
+                                                 const float2* __restrict__ twg) {
+  using S = FftShape<L>;
+  constexpr int ROWS = 256 / S::T;
+  __shared__ float2 tw[L];
+  __shared__ float2 bufs[ROWS][2][S::PAD];
+  __shared__ double red[4];
+  const int f = blockIdx.y;
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  const int n = blockIdx.x * ROWS + team;
+  load_twiddles<L>(tw, twg);
+  float2 val[8];
+  const float2* row = T + ((size_t)f * N + n) * L;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : make_float2(0.f, 0.f);
+  __syncthreads();
+  fft_team<L, true, false>(val, t, bufs[team][0], bufs[team][1], tw);
+  double acc = 0.0;
+  if (n < N) {
+    const size_t ro = ((size_t)f * N + n) * N;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int p = t + e * S::T;
+      if (p < N) {
+        out[ro + p] = val[e];
+        if (d) {
+          const float2 dv = d[ro + p];
+          acc += (double)dv.x * (double)val[e].x + (double)dv.y * (double)val[e].y;
+        }
+      }
+    }
+  }
+  if (d) {
+    double v1[1] = {acc};
+    block_sum<1>(v1, red);
+    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + blockIdx.x] = v1[0];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define RECON_L_SWITCH(L_, CALL)                         \
+  switch (L_) {                                          \
+    case 64: { constexpr int LL = 64; CALL; } break;     \
+    case 128: { constexpr int LL = 128; CALL; } break;   \
+    case 256: { constexpr int LL = 256; CALL; } break;   \
+    case 512: { constexpr int LL = 512; CALL; } break;   \
+    case 1024: { constexpr int LL = 1024; CALL; } break; \
+    case 2048: { constexpr int LL = 2048; CALL; } break; \
+    default: return hipErrorInvalidValue;                \
+  }
+
+hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
+                               const float2* tw, hipStream_t s) {
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_L_SWITCH(L, (k_rowfft_plain<LL><<<grid, 256, 0, s>>>(N, v, T, tw)));
+  return hipGetLastError();
+}
+
+hipError_t launch_rowfft_full(int L, int rows, float2* data, const float2* tw,
+                              hipStream_t s) {
+  dim3 grid(cdiv(rows, fft_rows_per_block(L)), 1);
+  RECON_L_SWITCH(L, (k_rowfft_full<LL><<<grid, 256, 0, s>>>(rows, data, tw)));
+  return hipGetLastError();
+}
+
+hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s,
+                          const float2* tw, hipStream_t s) {
+  dim3 grid(L / fft_cols_per_block(L), B);
+  switch (L) {
+    case 64: k_colpass<64, 32><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    case 128: k_colpass<128, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    case 256: k_colpass<256, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    case 512: k_colpass<512, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    case 1024: k_colpass<1024, 8><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    case 2048: k_colpass<2048, 8><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
+                          const float2* d, double* p3, const float2* tw,
+                          hipStream_t s) {
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, d, p3, tw)));
+  return hipGetLastError();
+}
+
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
+                             const float2* d_old, float2* d_new,
+                             const float2* x, float2* T, const double* p4,
+                             int nb4, double* p1, const FrameParam* fp,
+                             const float2* tw, hipStream_t s) {
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+#define RECON_DIR(PHI_)                                                       \
+  RECON_L_SWITCH(L, (k_dir_rowfft<LL, PHI_><<<grid, 256, 0, s>>>(             \
+                        N, g, d_old, d_new, x, T, p4, nb4, p1, fp, tw)))
+  switch (phi) {
+    case 0: RECON_DIR(0); break;
+    case 1: RECON_DIR(1); break;
+    case 2: RECON_DIR(2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RECON_DIR
+  return hipGetLastError();
+}
+
+}  // namespace recon

@@ -1,0 +1,259 @@
+"""ctypes binding of librecon.so (the C ABI in include/recon.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  PyTorch supplies device memory (complex64 / uint8 tensors) and the
+current HIP stream.  The library must have been built (``build.py``); a
+missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librecon.so")
+
+OK, E_ARG, E_RANGE, E_NOMEM, E_HIP, E_STATE, E_NONFINITE = range(7)
+FP32, BF16X3, FP16X3 = 0, 1, 2
+PHI = {"hyperbolic": 0, "huber": 1, "quadratic": 2}
+FIELD = {"x": 0, "r": 1, "g": 2, "d": 3, "b": 4}
+
+STATS_DTYPE = np.dtype([("J", "<f8"), ("grad_ratio", "<f8"), ("gnorm0", "<f8"),
+                        ("iters_done", "<i4"), ("status", "<i4")])
+
+_lib = None
+
+
+class ReconError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"recon status {status}: {detail}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          f"python -m paper_0908_3252_amd.build")
+    lib = ctypes.CDLL(path)
+    c = ctypes
+    vp, i32, i64, sz, f32 = c.c_void_p, c.c_int32, c.c_int64, c.c_size_t, c.c_float
+    sig = {
+        "recon_plan_bytes": (sz, [i64, i32, i32, i32]),
+        "recon_gram_workspace_bytes": (sz, [i64, i32, i32]),
+        "recon_workspace_bytes": (sz, [i64, i32, i32, i32]),
+        "recon_plan": (i32, [vp, i64, i32, i32, i32, vp, sz, vp, c.POINTER(vp)]),
+        "recon_plan_info": (i32, [vp, c.POINTER(i64), c.POINTER(i32), c.POINTER(i32),
+                                  c.POINTER(i32)]),
+        "recon_plan_destroy": (None, [vp]),
+        "recon_gram_kernel": (i32, [vp, vp, sz, vp, vp, vp]),
+        "recon_adjoint": (i32, [vp, vp, i32, vp, vp, vp, sz, vp]),
+        "recon_forward": (i32, [vp, vp, i32, vp, vp, sz, vp]),
+        "recon_gram_apply": (i32, [vp, vp, i32, vp, vp, sz, vp]),
+        "recon_solve": (i32, [vp, vp, i32, f32, f32, i32, i32, vp, i32, vp, sz, vp, vp]),
+        "recon_solve_begin": (i32, [vp, vp, vp, i32, f32, f32, i32, vp, vp, sz, vp]),
+        "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
+        "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
+        "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
+        "recon_trace_enable": (i32, [i32, i32]),
+        "recon_trace_read": (i32, [c.POINTER(c.c_float), i32]),
+        "recon_status_string": (c.c_char_p, [i32]),
+        "recon_last_error": (c.c_char_p, []),
+        "recon_version": (c.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        lib = load()
+        raise ReconError(status, lib.recon_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_buf(nbytes: int):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def default_L(N: int) -> int:
+    L = 64
+    while L < 2 * N - 1:
+        L *= 2
+    return L
+
+
+class Plan:
+    """A trajectory on the device plus its Gram spectrum (after gram_kernel)."""
+
+    def __init__(self, k: np.ndarray, N: int, L: int = 0, prec: int = FP32):
+        lib = load()
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+        if k.ndim != 2 or k.shape[1] != 2:
+            raise ValueError("trajectory must have shape [M, 2]")
+        self.M = int(k.shape[0])
+        self.N = int(N)
+        self.L = int(L) if L else default_L(N)
+        self.prec = int(prec)
+        nbytes = lib.recon_plan_bytes(self.M, self.N, self.L, self.prec)
+        if nbytes == 0:
+            raise ReconError(E_RANGE, "invalid plan geometry")
+        self.mem = _dev_buf(nbytes)
+        h = ctypes.c_void_p()
+        _check(lib.recon_plan(k.ctypes.data, self.M, self.N, self.L, self.prec,
+                              self.mem.data_ptr(), nbytes, _stream(), ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.recon_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, B: int):
+        """Device workspace for B frames (cached per B)."""
+        if B not in self._ws:
+            n = load().recon_workspace_bytes(self.M, self.N, self.L, B)
+            self._ws[B] = (_dev_buf(n), n)
+        return self._ws[B]
+
+    def gram_kernel(self, want_khat: bool = False, want_lag: bool = False):
+        import torch
+        lib = load()
+        n = lib.recon_gram_workspace_bytes(self.M, self.N, self.L)
+        ws = _dev_buf(n)
+        khat = torch.empty((self.L, self.L), dtype=torch.float32, device="cuda") if want_khat else None
+        lag = (torch.empty((2 * self.N - 1, 2 * self.N - 1), dtype=torch.complex128, device="cuda")
+               if want_lag else None)
+        _check(lib.recon_gram_kernel(self._h, ws.data_ptr(), n, _ptr(khat), _ptr(lag), _stream()))
+        torch.cuda.current_stream().synchronize()
+        del ws
+        return khat, lag
+
+    def adjoint(self, y, want_yy: bool = False):
+        import torch
+        y = y.contiguous()
+        B = y.shape[0]
+        b = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
+        yy = torch.empty(B, dtype=torch.float64, device="cuda") if want_yy else None
+        ws, n = self.workspace(B)
+        _check(load().recon_adjoint(self._h, y.data_ptr(), B, b.data_ptr(), _ptr(yy),
+                                    ws.data_ptr(), n, _stream()))
+        return (b, yy) if want_yy else b
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        B = x.shape[0]
+        y = torch.empty((B, self.M), dtype=torch.complex64, device="cuda")
+        ws, n = self.workspace(B)
+        _check(load().recon_forward(self._h, x.data_ptr(), B, y.data_ptr(), ws.data_ptr(), n,
+                                    _stream()))
+        return y
+
+    def gram_apply(self, v):
+        import torch
+        v = v.contiguous()
+        B = v.shape[0]
+        out = torch.empty_like(v)
+        ws, n = self.workspace(B)
+        _check(load().recon_gram_apply(self._h, v.data_ptr(), B, out.data_ptr(), ws.data_ptr(),
+                                       n, _stream()))
+        return out
+
+    def solve(self, y, lam: float, delta: float, iters: int, phi: str = "hyperbolic",
+              x0=None, want_stats: bool = True):
+        import torch
+        y = y.contiguous()
+        B = y.shape[0]
+        x = (x0.clone().contiguous() if x0 is not None else
+             torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda"))
+        st = _dev_buf(B * STATS_DTYPE.itemsize) if want_stats else None
+        ws, n = self.workspace(B)
+        _check(load().recon_solve(self._h, y.data_ptr(), B, float(lam), float(delta), int(iters),
+                                  PHI[phi], x.data_ptr(), 1 if x0 is not None else 0,
+                                  ws.data_ptr(), n, _ptr(st), _stream()))
+        if not want_stats:
+            return x
+        return x, stats_to_numpy(st, B)
+
+    # resumable form
+    def begin(self, y=None, b=None, B=None, lam=0.0, delta=1.0, phi="hyperbolic", x0=None):
+        src = y if y is not None else b
+        B = src.shape[0] if B is None else B
+        ws, n = self.workspace(B)
+        _check(load().recon_solve_begin(self._h, _ptr(y), _ptr(b), B, float(lam), float(delta),
+                                        PHI[phi], _ptr(x0), ws.data_ptr(), n, _stream()))
+        self._active_B = B
+
+    def iterate(self, iters: int):
+        ws, n = self.workspace(self._active_B)
+        _check(load().recon_solve_iterate(self._h, int(iters), ws.data_ptr(), n, _stream()))
+
+    def export(self, field: str):
+        import torch
+        B = self._active_B
+        out = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
+        ws, n = self.workspace(B)
+        _check(load().recon_solve_export(self._h, FIELD[field], out.data_ptr(), ws.data_ptr(), n,
+                                         _stream()))
+        return out
+
+    def end(self):
+        import torch
+        B = self._active_B
+        x = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
+        st = _dev_buf(B * STATS_DTYPE.itemsize)
+        ws, n = self.workspace(B)
+        _check(load().recon_solve_end(self._h, x.data_ptr(), st.data_ptr(), ws.data_ptr(), n,
+                                      _stream()))
+        return x, stats_to_numpy(st, B)
+
+
+TRACE = {"dir_rowfft": 0, "colpass": 1, "rowifft": 2, "update": 3, "adjoint": 4, "gram": 5,
+         "forward": 6}
+
+
+def trace_enable(kernel: Optional[str], capacity: int = 4096):
+    """Record HIP events around each launch of one kernel kind (None: off)."""
+    _check(load().recon_trace_enable(-1 if kernel is None else TRACE[kernel], int(capacity)))
+
+
+def trace_read(n: int = 1 << 16) -> np.ndarray:
+    buf = (ctypes.c_float * n)()
+    m = load().recon_trace_read(buf, n)
+    if m < 0:
+        raise ReconError(E_HIP, "trace read failed")
+    return np.array(buf[:m], dtype=np.float64)
+
+
+def stats_to_numpy(st, B: int) -> np.ndarray:
+    import torch
+    torch.cuda.current_stream().synchronize()
+    raw = st[: B * STATS_DTYPE.itemsize].cpu().numpy()
+    return np.frombuffer(raw.tobytes(), dtype=STATS_DTYPE).copy()
