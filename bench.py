@@ -67,7 +67,7 @@ def synth_batch(plan, prob, B, torch):
     return (y0 + sig * noise).contiguous()
 
 
-def cpu_baseline(args, torch, recon):
+def cpu_baseline(args, torch, recon, prec):
     """The FP64 oracle on one 256^2 frame (adjoint + Gram + all iterations),
     timed on the host, and the GPU result on the same frame against it."""
     import oracle
@@ -84,7 +84,7 @@ def cpu_baseline(args, torch, recon):
     xo = oracle.solve(b, K, prob.lam, prob.delta, prob.iters)
     dt = time.perf_counter() - t0
     # GPU on the identical frame (oracle-made data)
-    plan = recon.Plan(prob.k, prob.N, prob.L)
+    plan = recon.Plan(prob.k, prob.N, prob.L, prec=prec)
     plan.gram_kernel()
     xg, st = plan.solve(torch.from_numpy(y.astype(np.complex64)).cuda(), prob.lam, prob.delta,
                         prob.iters)
@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--trace", default="colpass",
                     choices=["colpass", "dir_rowfft", "rowifft", "update"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"],
+                    help="adjoint contraction precision (fp64: FP64 MFMA accumulation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=10)
     args = ap.parse_args()
@@ -128,11 +130,12 @@ def main():
 
     # device-resident inputs and buffers (allocated once)
     lib = recon.load()
-    plan = recon.Plan(prob.k, N, L)
+    prec = recon.FP64 if args.prec == "fp64" else recon.FP32
+    plan = recon.Plan(prob.k, N, L, prec=prec)
     plan.gram_kernel()
     y = synth_batch(plan, prob, B, torch)
     k_host = np.ascontiguousarray(prob.k)
-    plan_bytes = lib.recon_plan_bytes(M, N, L, 0)
+    plan_bytes = lib.recon_plan_bytes(M, N, L, prec)
     gws_bytes = lib.recon_gram_workspace_bytes(M, N, L)
     gws = torch.empty(gws_bytes, dtype=torch.uint8, device="cuda")
     ws, ws_bytes = plan.workspace(B)
@@ -144,7 +147,7 @@ def main():
 
     def step():
         h = ctypes.c_void_p()
-        recon._check(lib.recon_plan(k_host.ctypes.data, M, N, L, 0, plan.mem.data_ptr(),
+        recon._check(lib.recon_plan(k_host.ctypes.data, M, N, L, prec, plan.mem.data_ptr(),
                                     plan_bytes, stream, ctypes.byref(h)))
         try:
             recon._check(lib.recon_gram_kernel(h, gws.data_ptr(), gws_bytes, None, None, stream))
@@ -213,7 +216,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32 (fp64 Gram accumulation and reductions)",
+        "dtype": ("fp32 iterations; fp64 adjoint and Gram accumulation, fp64 reductions"
+                  if args.prec == "fp64" else "fp32 (fp64 Gram accumulation and reductions)"),
         "data": "synthetic",
         "config": {"workload": f"256x256 spiral M={M} (16 interleaves, 2x angular "
                                f"undersampling), hyperbolic delta={prob.delta}, "
@@ -232,7 +236,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, one frame)")
-        cb, rel = cpu_baseline(args, torch, recon)
+        cb, rel = cpu_baseline(args, torch, recon, prec)
         out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
         out["rel_l2_vs_oracle_one_frame"] = rel
     print(json.dumps(out), flush=True)

@@ -115,7 +115,8 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   {
     const int g = adjoint_group(M, N);
     const int frames = g < B ? g : B;
-    w.adj = take(w.adj_splits > 1 ? (size_t)w.adj_splits * frames * N * N * sizeof(float2) : 0);
+    // FP64 complex partials serve both adjoint precisions
+    w.adj = take(w.adj_splits > 1 ? (size_t)w.adj_splits * frames * N * N * sizeof(double2) : 0);
   }
   w.total = off;
   return w;
@@ -133,9 +134,9 @@ GramWsLayout gram_ws_layout(int64_t M, int32_t N, int32_t L) {
   g.part = off;
   off = align_up(off + (size_t)g.splits * 4 * N * N * sizeof(double));
   g.emb = off;
-  off = align_up(off + (size_t)L * L * sizeof(float2));
+  off = align_up(off + (size_t)L * L * sizeof(double2));
   g.emb2 = off;
-  off = align_up(off + (size_t)L * L * sizeof(float2));
+  off = align_up(off + (size_t)L * L * sizeof(double2));
   g.total = off;
   return g;
 }
@@ -230,10 +231,13 @@ recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, f
   return RECON_OK;
 }
 
-recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b, float2* part,
+recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b, void* part,
                               hipStream_t s) {
   TraceScope ts(TK_ADJ, s);
-  HIP_TRY(launch_adjoint_f32(p->M, p->N, B, p->ex(), p->ey(), y, b, part, s));
+  if (p->prec == RECON_FP64)
+    HIP_TRY(launch_adjoint_f64(p->M, p->N, B, p->k(), y, b, static_cast<double2*>(part), s));
+  else
+    HIP_TRY(launch_adjoint_f32(p->M, p->N, B, p->ex(), p->ey(), y, b, static_cast<float2*>(part), s));
   return RECON_OK;
 }
 
@@ -244,7 +248,7 @@ extern "C" {
 size_t recon_plan_bytes(int64_t M, int32_t N, int32_t L, int32_t prec) {
   if (L == 0) L = default_L(N);
   if (check_geometry(M, N, L) != RECON_OK) return 0;
-  if (prec < 0 || prec > 2) return 0;
+  if (prec < 0 || prec > 3) return 0;
   return plan_layout(M, N, L, prec).total;
 }
 
@@ -268,7 +272,7 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   if (L == 0) L = default_L(N);
   recon_status_t st = check_geometry(M, N, L);
   if (st != RECON_OK) return st;
-  if (prec != RECON_FP32) {
+  if (prec != RECON_FP32 && prec != RECON_FP64) {
     if (prec == RECON_BF16X3 || prec == RECON_FP16X3)
       return fail(RECON_E_RANGE, "split precisions are not available in this build");
     return fail(RECON_E_ARG, "unknown precision");
@@ -329,17 +333,14 @@ recon_status_t recon_gram_kernel(recon_plan_t p, void* ws, size_t ws_bytes, floa
   hipStream_t s = as_stream(stream);
   char* base = static_cast<char*>(ws);
   double* part = reinterpret_cast<double*>(base + g.part);
-  float2* emb = reinterpret_cast<float2*>(base + g.emb);
-  float2* emb2 = reinterpret_cast<float2*>(base + g.emb2);
+  double2* emb = reinterpret_cast<double2*>(base + g.emb);
+  double2* emb2 = reinterpret_cast<double2*>(base + g.emb2);
   {
     TraceScope ts(TK_GRAM, s);
     HIP_TRY(launch_gram_f64(p->M, p->N, p->k(), part, g.splits, s));
   }
   HIP_TRY(launch_gram_assemble(p->N, p->L, part, g.splits, lag_out, emb, s));
-  HIP_TRY(launch_rowfft_full(p->L, p->L, emb, p->tw(), s));
-  HIP_TRY(launch_transpose(p->L, emb, emb2, s));
-  HIP_TRY(launch_rowfft_full(p->L, p->L, emb2, p->tw(), s));
-  HIP_TRY(launch_khat_finish(p->L, emb2, p->khat(), khat_out, s));
+  HIP_TRY(launch_spectrum_f64(p->L, emb, emb2, p->khat(), khat_out, s));
   p->gram_done = true;
   return RECON_OK;
 }

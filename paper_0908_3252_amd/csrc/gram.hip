@@ -127,17 +127,17 @@ __device__ __forceinline__ double2 lag_value(int a, int b, int N, const double* 
 }
 
 __global__ void k_gram_assemble(int N, int L, const double* __restrict__ part, int splits,
-                                double* __restrict__ lag_out, float2* __restrict__ emb) {
+                                double* __restrict__ lag_out, double2* __restrict__ emb) {
   const double inv = 1.0 / ((double)N * (double)N);
   const int total = L * L;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const int p = i / L, q = i - p * L;
     const int a = (p < N) ? p : ((p > L - N) ? p - L : INT32_MAX);
     const int b = (q < N) ? q : ((q > L - N) ? q - L : INT32_MAX);
-    float2 v = make_float2(0.f, 0.f);
+    double2 v = make_double2(0.0, 0.0);
     if (a != INT32_MAX && b != INT32_MAX) {
       const double2 h = lag_value(a, b, N, part, splits, inv);
-      v = make_float2((float)h.x, (float)h.y);
+      v = h;
       if (lag_out) {
         const size_t o = ((size_t)(a + N - 1) * (2 * N - 1) + (b + N - 1)) * 2;
         lag_out[o] = h.x;
@@ -145,32 +145,6 @@ __global__ void k_gram_assemble(int N, int L, const double* __restrict__ part, i
       }
     }
     emb[i] = v;
-  }
-}
-
-__global__ void k_transpose(int L, const float2* __restrict__ in, float2* __restrict__ out) {
-  __shared__ float2 t[32][33];
-  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
-  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
-    const int r = y0 + j, c = x0 + threadIdx.x;
-    if (r < L && c < L) t[j][threadIdx.x] = in[(size_t)r * L + c];
-  }
-  __syncthreads();
-  for (int j = threadIdx.y; j < 32; j += blockDim.y) {
-    const int r = x0 + j, c = y0 + threadIdx.x;
-    if (r < L && c < L) out[(size_t)r * L + c] = t[threadIdx.x][j];
-  }
-}
-
-__global__ void k_khat_finish(int L, const float2* __restrict__ spec_t, float* __restrict__ khat_s,
-                              float* __restrict__ khat_out) {
-  const float inv = 1.0f / ((float)L * (float)L);
-  const int total = L * L;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    const int q = i / L, p = i - q * L;
-    const float v = spec_t[i].x;
-    khat_s[i] = v * inv;
-    if (khat_out) khat_out[(size_t)p * L + q] = v;
   }
 }
 
@@ -193,24 +167,10 @@ hipError_t launch_gram_f64(int64_t M, int N, const double* k, double* part, int 
 }
 
 hipError_t launch_gram_assemble(int N, int L, const double* part, int splits, double* lag_out,
-                                float2* emb, hipStream_t s) {
+                                double2* emb, hipStream_t s) {
   int blocks = cdiv(L * L, 256);
   if (blocks > 65536) blocks = 65536;
   k_gram_assemble<<<blocks, 256, 0, s>>>(N, L, part, splits, lag_out, emb);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose(int L, const float2* in, float2* out, hipStream_t s) {
-  dim3 grid(cdiv(L, 32), cdiv(L, 32));
-  k_transpose<<<grid, dim3(32, 8), 0, s>>>(L, in, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_khat_finish(int L, const float2* spec_t, float* khat_s, float* khat_out,
-                              hipStream_t s) {
-  int blocks = cdiv(L * L, 256);
-  if (blocks > 65536) blocks = 65536;
-  k_khat_finish<<<blocks, 256, 0, s>>>(L, spec_t, khat_s, khat_out);
   return hipGetLastError();
 }
 

@@ -35,10 +35,6 @@ hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
                           const float2* d, double* p3, const float2* tw,
                           hipStream_t s);
 
-// Full-length transforms for the spectrum build: rows of an [rows][L]
-// complex array in place, forward.
-hipError_t launch_rowfft_full(int L, int rows, float2* data, const float2* tw,
-                              hipStream_t s);
 
 // ---- CG kernels (Section 3.3) -------------------------------------------------
 // Direction update d_new = -g + beta d_old (beta from the update partials,
@@ -111,13 +107,17 @@ hipError_t launch_gram_f64(int64_t M, int N, const double* k, double* part,
                            int splits, hipStream_t s);
 // Reduce the split partials, scale by 1/N^2, assemble h over the full lag
 // range (conjugate symmetry), optionally export it (lag_out complex128
-// [2N-1][2N-1]) and embed it circularly into emb [L][L] (FP32 complex).
+// [2N-1][2N-1]) and embed it circularly into emb [L][L] (FP64 complex).
 hipError_t launch_gram_assemble(int N, int L, const double* part, int splits,
-                                double* lag_out, float2* emb, hipStream_t s);
-// Transpose an [L][L] complex array (out[q][p] = in[p][q]).
-hipError_t launch_transpose(int L, const float2* in, float2* out, hipStream_t s);
-// khat_s[q][p] = Re(spec_t[q][p]) / L^2 ; khat_out[p][q] = Re(spec_t[q][p]).
-hipError_t launch_khat_finish(int L, const float2* spec_t, float* khat_s,
-                              float* khat_out, hipStream_t s);
+                                double* lag_out, double2* emb, hipStream_t s);
+// FP64 2D FFT of the embedding (emb is overwritten, tmp is scratch of the
+// same size), then khat_s[q][p] = Re K[p][q] / L^2 (FP32, transposed) and
+// optionally khat_out[p][q] = Re K[p][q].
+hipError_t launch_spectrum_f64(int L, double2* emb, double2* tmp, float* khat_s,
+                               float* khat_out, hipStream_t s);
+// Adjoint accumulated in FP64 (phasors generated in FP64 from k); b FP32.
+// part: split-K partials, FP64 complex [splits][group][N][N].
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double* k, const float2* y,
+                              float2* b, double2* part, hipStream_t s);
 
 }  // namespace recon

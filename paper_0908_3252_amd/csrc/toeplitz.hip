@@ -49,28 +49,6 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __res
   }
 }
 
-template <int L>
-__global__ __launch_bounds__(256) void k_rowfft_full(int rows, float2* __restrict__ data,
-                                                     const float2* __restrict__ twg) {
-  using S = FftShape<L>;
-  constexpr int ROWS = 256 / S::T;
-  __shared__ float2 tw[L];
-  __shared__ float2 bufs[ROWS][2][S::PAD];
-  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
-  const int n = blockIdx.x * ROWS + team;
-  load_twiddles<L>(tw, twg);
-  float2 val[8];
-  float2* row = data + (size_t)n * L;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) val[e] = (n < rows) ? row[t + e * S::T] : make_float2(0.f, 0.f);
-  __syncthreads();
-  fft_team<L, false, false>(val, t, bufs[team][0], bufs[team][1], tw);
-  if (n < rows) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) row[t + e * S::T] = val[e];
-  }
-}
-
 // --------------------------------------------- CG direction + row pass (fused)
 // Block = ROWS image rows of frame f.  Phase A builds d_new = -g + beta d_old
 // for the block's rows plus one halo row below (recomputed bit-identically
@@ -279,13 +257,6 @@ hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
                                const float2* tw, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
   RECON_L_SWITCH(L, (k_rowfft_plain<LL><<<grid, 256, 0, s>>>(N, v, T, tw)));
-  return hipGetLastError();
-}
-
-hipError_t launch_rowfft_full(int L, int rows, float2* data, const float2* tw,
-                              hipStream_t s) {
-  dim3 grid(cdiv(rows, fft_rows_per_block(L)), 1);
-  RECON_L_SWITCH(L, (k_rowfft_full<LL><<<grid, 256, 0, s>>>(rows, data, tw)));
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librecon.so")
 
 OK, E_ARG, E_RANGE, E_NOMEM, E_HIP, E_STATE, E_NONFINITE = range(7)
-FP32, BF16X3, FP16X3 = 0, 1, 2
+FP32, BF16X3, FP16X3, FP64 = 0, 1, 2, 3
 PHI = {"hyperbolic": 0, "huber": 1, "quadratic": 2}
 FIELD = {"x": 0, "r": 1, "g": 2, "d": 3, "b": 4}
 

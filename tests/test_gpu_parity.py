@@ -51,18 +51,24 @@ CASES = [
 ]
 
 
+# adjoint error bound per precision: FP32 accumulation over M samples
+# (~3e-7 measured), FP64 accumulation then one rounding to FP32 (~3e-8).
+ADJ_TOL = {recon.FP32: 2e-6, recon.FP64: 1e-7}
+
+
+@pytest.mark.parametrize("prec", [recon.FP32, recon.FP64])
 @pytest.mark.parametrize("name,N,karg,B", CASES)
-def test_adjoint_and_forward(name, N, karg, B):
+def test_adjoint_and_forward(name, N, karg, B, prec):
     """Eq. AnnMatGD (b = A^H y) and Eq. ModDirect (y = A x) vs the oracle."""
-    rng = np.random.default_rng(hash(name) % 2**31)
+    rng = np.random.default_rng(abs(hash(name)) % 2**31)
     k = spiral(N, *karg)
-    plan = recon.Plan(k, N)
+    plan = recon.Plan(k, N, prec=prec)
     y = rand_c(rng, B, k.shape[0])
-    b_ref = oracle.adjoint(y, k, N)
+    b_ref = oracle.adjoint(y.astype(np.complex64), k, N)
     b = host(plan.adjoint(dev(y)))
     e = rel(b, b_ref)
-    print(f"{name}: adjoint rel {e:.2e}")
-    assert e < 2e-6
+    print(f"{name} prec={prec}: adjoint rel {e:.2e}")
+    assert e < ADJ_TOL[prec]
     x = rand_c(rng, B, N, N)
     y_ref = oracle.forward(x, k)
     yg = host(plan.forward(dev(x)))
@@ -71,20 +77,21 @@ def test_adjoint_and_forward(name, N, karg, B):
     assert e < 2e-6
     # per-frame agreement too
     for f in range(B):
-        assert rel(b[f], b_ref[f]) < 2e-6
+        assert rel(b[f], b_ref[f]) < ADJ_TOL[prec]
 
 
-def test_adjoint_full_size_workload():
+@pytest.mark.parametrize("prec", [recon.FP32, recon.FP64])
+def test_adjoint_full_size_workload(prec):
     """256^2 image, M = 32768 spiral samples (single frame), full comparison."""
     p = synthetic.make_problem(2)
-    plan = recon.Plan(p.k, p.N)
+    plan = recon.Plan(p.k, p.N, prec=prec)
     rng = np.random.default_rng(5)
-    y = rand_c(rng, 1, p.M)
+    y = rand_c(rng, 1, p.M).astype(np.complex64)
     b_ref = oracle.adjoint(y, p.k, p.N)
     b, yy = plan.adjoint(dev(y), want_yy=True)
     e = rel(host(b), b_ref)
-    print(f"adjoint 256/32768 rel {e:.2e}")
-    assert e < 2e-6
+    print(f"adjoint 256/32768 prec={prec} rel {e:.2e}")
+    assert e < ADJ_TOL[prec]
     torch.cuda.synchronize()
     yy_ref = np.sum(np.abs(y.astype(np.complex64).astype(np.complex128)) ** 2)
     assert abs(float(yy.cpu()[0]) - yy_ref) < 1e-12 * yy_ref
@@ -106,7 +113,7 @@ def test_gram_kernel_and_spectrum(N, L, karg):
     K = khat.cpu().numpy().astype(np.float64)
     e = float(np.abs(K - K_ref).max() / np.abs(K_ref).max())
     print(f"N={N} L={L}: khat max-rel {e:.2e}")
-    assert e < 1e-5
+    assert e < 2e-7  # FP64 FFT, one rounding to FP32
 
 
 @pytest.mark.parametrize("N,L,karg,B", [(32, 64, (4, 256, 1.0), 1), (48, 128, (5, 199, 1.0), 2),
@@ -258,3 +265,26 @@ def test_warm_start_matches_oracle():
     e = rel(host(x)[0], xo)
     print(f"warm start rel {e:.2e}")
     assert e < 1e-4
+
+
+@pytest.mark.parametrize("prec,bound", [(recon.FP64, 1e-4), (recon.FP32, 1e-3)])
+def test_end_to_end_plain_workload(prec, bound):
+    """256x256, M = 32768, 300 iterations (the benchmark's frame): the GPU
+    iterate against the FP64 oracle's iterate from the same data.  With the
+    FP64-accumulated adjoint the required 1e-4 holds; the FP32 adjoint's
+    ~3e-7 error in b is amplified by the iteration (measured ~2.5e-4) and
+    is reported against a 1e-3 bound."""
+    p = synthetic.make_problem(2)
+    y = p.measured(oracle.forward(p.x_true, p.k)).astype(np.complex64)
+    plan = recon.Plan(p.k, p.N, p.L, prec=prec)
+    plan.gram_kernel()
+    x, st = plan.solve(dev(y), p.lam, p.delta, p.iters)
+    b = oracle.adjoint(y[0], p.k, p.N)
+    K = oracle.khat(p.k, p.N, p.L)
+    yy = float(np.sum(np.abs(y[0].astype(np.complex128)) ** 2))
+    xo, h = oracle.solve(b, K, p.lam, p.delta, p.iters, yy=yy, history=True)
+    e = rel(host(x)[0], xo)
+    print(f"256^2 end-to-end prec={prec}: rel {e:.3e}; J gpu {st['J'][0]:.9g} oracle "
+          f"{h['J'][-1]:.9g}; grad ratio {st['grad_ratio'][0]:.3e} vs {h['gnorm'][-1] / h['gnorm'][0]:.3e}")
+    assert e < bound
+    assert abs(st["J"][0] - h["J"][-1]) < 1e-5 * abs(h["J"][-1])
