@@ -51,8 +51,8 @@ def kernel_bytes(kind: str, N: int, L: int, B: int) -> float:
         return colpass_bytes(N, L, B)
     if kind == "dir_rowfft":   # read g, d_old, x; write d, T (N x L)
         return B * (3 * img + img + 8.0 * N * L)
-    if kind == "rowifft":      # read T, d; write Qd
-        return B * (8.0 * N * L + 2 * img)
+    if kind == "rowifft":      # read T; write Qd
+        return B * (8.0 * N * L + img)
     if kind == "update":       # read x, d, r, Qd, g; write x, r, g
         return B * 8 * img
     raise ValueError(kind)

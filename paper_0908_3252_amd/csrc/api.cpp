@@ -102,7 +102,7 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   w.qd = take(img);
   w.T = take((size_t)B * N * L * sizeof(float2));
   w.nb1 = cdiv(N, fft_rows_per_block(L));
-  w.nb3 = w.nb1;
+  w.nb3 = L / fft_cols_per_block(L);  // <d, Qd> partials come from the column pass
   w.nb4 = cdiv(N, upd_rows_per_block(N));
   w.p1 = take((size_t)B * w.nb1 * 2 * sizeof(double));
   w.p3 = take((size_t)B * w.nb3 * sizeof(double));
@@ -216,17 +216,17 @@ recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// Q v for B frames into out (T: N x L scratch per frame); optional <d, Qd> partials.
+// Q v for B frames into out (T: N x L scratch per frame); optional <v, Qv> partials.
 recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, float2* T,
-                          const float2* d, double* p3, hipStream_t s) {
+                          double* p3, hipStream_t s) {
   HIP_TRY(launch_rowfft_plain(p->L, p->N, B, v, T, p->tw(), s));
   {
     TraceScope ts(TK_COL, s);
-    HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat(), p->tw(), s));
+    HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat(), p3, p->tw(), s));
   }
   {
     TraceScope ts(TK_ROWINV, s);
-    HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, d, p3, p->tw(), s));
+    HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, p->tw(), s));
   }
   return RECON_OK;
 }
@@ -381,7 +381,7 @@ recon_status_t recon_gram_apply(recon_plan_t p, const float* v, int32_t B, float
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
   if (st != RECON_OK) return st;
   return gram_apply(p, reinterpret_cast<const float2*>(v), reinterpret_cast<float2*>(Qv), B,
-                    w.img(w.lay.T), nullptr, nullptr, as_stream(stream));
+                    w.img(w.lay.T), nullptr, as_stream(stream));
 }
 
 recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
@@ -415,7 +415,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   const float2* qx0 = nullptr;
   if (x0) {
     recon_status_t r = gram_apply(p, reinterpret_cast<const float2*>(x0), w.img(w.lay.qd), B,
-                                  w.img(w.lay.T), nullptr, nullptr, s);
+                                  w.img(w.lay.T), nullptr, s);
     if (r != RECON_OK) return r;
     qx0 = w.img(w.lay.qd);
   }
@@ -467,11 +467,11 @@ recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size
     }
     {
       TraceScope ts(TK_COL, s);
-      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), p->tw(), s));
+      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), w.dbl(w.lay.p3), p->tw(), s));
     }
     {
       TraceScope ts(TK_ROWINV, s);
-      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), d_new, w.dbl(w.lay.p3), p->tw(), s));
+      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), p->tw(), s));
     }
     {
       TraceScope ts(TK_UPDATE, s);

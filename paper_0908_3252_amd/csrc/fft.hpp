@@ -143,6 +143,26 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[8], int t, const float2* tw
   }
 }
 
+// Ordering of the LDS exchanges of a team.  A team that fits in one
+// wavefront (L <= 512) needs no block barrier: LDS operations of a wave are
+// performed in issue order, so a compiler-level fence between the writes and
+// the reads of an exchange suffices, and one buffer can serve every pass.
+// Larger teams span several waves and use block barriers with two buffers.
+template <int L>
+struct FftSync {
+  static constexpr bool WAVE_LOCAL = FftShape<L>::T <= 64;
+};
+
+template <int L>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (FftSync<L>::WAVE_LOCAL) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int L, bool INV, bool HALF_IN, int P, int NS>
 __device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
                                            float2* buf1, const float2* tw) {
@@ -152,21 +172,24 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
   int pos[8];
   fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
   if constexpr (P + 1 < S::NP) {
-    float2* buf = (P & 1) ? buf1 : buf0;
+    float2* buf = (FftSync<L>::WAVE_LOCAL || !(P & 1)) ? buf0 : buf1;
 #pragma unroll
     for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
-    __syncthreads();
+    team_sync<L>();
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = buf[lpad(t + e * S::T)];
+    if constexpr (FftSync<L>::WAVE_LOCAL) team_sync<L>();  // reads before next writes
     fft_passes<L, INV, HALF_IN, P + 1, NS * R>(v, t, buf0, buf1, tw);
   }
   // Last pass: j < L/R = NS, so pos[e] = t + e*T and v is already in the
   // strided output layout.
 }
 
-// Full transform.  Every thread of the block must call this (it contains
-// block barriers).  buf0/buf1: this team's two LDS buffers of PAD entries;
-// tw: LDS table tw[i] = exp(-2 pi i i / L), i < L.
+// Full transform.  For L > 512 every thread of the block must call this
+// (block barriers); for L <= 512 only the team's own wavefront is involved.
+// buf0/buf1: this team's LDS buffers of PAD entries (buf1 unused when the
+// team is wave-local; it may then alias buf0); tw: LDS table
+// tw[i] = exp(-2 pi i i / L), i < L.
 template <int L, bool INV, bool HALF_IN>
 __device__ __forceinline__ void fft_team(float2 (&v)[8], int t, float2* buf0,
                                          float2* buf1, const float2* tw) {
@@ -175,6 +198,12 @@ __device__ __forceinline__ void fft_team(float2 (&v)[8], int t, float2* buf0,
     for (int e = 4; e < 8; ++e) v[e] = make_float2(0.f, 0.f);
   }
   fft_passes<L, INV, HALF_IN, 0, 1>(v, t, buf0, buf1, tw);
+}
+
+// LDS entries one team needs for its exchange buffers.
+template <int L>
+constexpr int fft_team_lds() {
+  return (FftSync<L>::WAVE_LOCAL ? 1 : 2) * FftShape<L>::PAD;
 }
 
 // Copy the plan's twiddle table (global) into LDS.

@@ -15,9 +15,9 @@ struct FrameParam {
 // Rows handled by one 256-thread block of the row-FFT kernels.
 inline int fft_rows_per_block(int L) { return 2048 / L; }
 // Columns handled by one block of the column kernel.
-inline int fft_cols_per_block(int L) { return L <= 64 ? 32 : (L <= 512 ? 16 : 8); }
+int fft_cols_per_block(int L);
 // Rows per block of the elementwise update kernel.
-inline int upd_rows_per_block(int N) { return N >= 256 ? 2 : (N >= 64 ? 4 : 8); }
+inline int upd_rows_per_block(int N) { return N > 512 ? 4 : 8; }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -27,13 +27,13 @@ hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
                                const float2* tw, hipStream_t s);
 // Column pass (in place): column q of T[f] -> IFFT_L(khat_s[q][:] * FFT_L(col)),
 // rows n < N kept.  khat_s is the transposed spectrum scaled by 1/L^2.
-hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s,
+// p3 (optional, [B][L / cols_per_block]) receives per-block partials of
+// sum khat_s |FFT_L(col)|^2 = Re<v, Q v> (Parseval).
+hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
                           const float2* tw, hipStream_t s);
-// Row inverse pass: out[f][n][m] = IFFT_L(T[f][n][:])[m] for m < N.  With
-// d != NULL also writes per-block partials Re<d, out> to p3[f][blk].
+// Row inverse pass: out[f][n][m] = IFFT_L(T[f][n][:])[m] for m < N.
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
-                          const float2* d, double* p3, const float2* tw,
-                          hipStream_t s);
+                          const float2* tw, hipStream_t s);
 
 
 // ---- CG kernels (Section 3.3) -------------------------------------------------

@@ -12,13 +12,23 @@
 //                                           in place, tiles staged in LDS)
 //   row inverse   T[N][L]  -> Qv[N][N]     (row IFFTs, first N outputs kept)
 // The direction update of the conjugate gradient (and its step-length
-// partials) is fused into the row pass; the <d, Qd> partial into the
-// inverse row pass.
+// partials) is fused into the row pass; the <d, Qd> partial is taken in the
+// column pass (Parseval).
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
 
 namespace recon {
+
+// Exchange buffers of one team inside a block-shared array.
+template <int L>
+__device__ __forceinline__ float2* team_buf0(float2* base, int team) {
+  return base + team * fft_team_lds<L>();
+}
+template <int L>
+__device__ __forceinline__ float2* team_buf1(float2* base, int team) {
+  return team_buf0<L>(base, team) + (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD);
+}
 
 // ----------------------------------------------------------------- row pass
 template <int L>
@@ -28,7 +38,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __res
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   __shared__ float2 tw[L];
-  __shared__ float2 bufs[ROWS][2][S::PAD];
+  __shared__ float2 bufs[ROWS * fft_team_lds<L>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
@@ -41,7 +51,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __res
     val[e] = (n < N && p < N) ? row[p] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_team<L, false, true>(val, t, bufs[team][0], bufs[team][1], tw);
+  fft_team<L, false, true>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
   if (n < N) {
     float2* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
@@ -63,7 +73,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   constexpr int TILE = (ROWS + 1) * (L / 2);
-  constexpr int FFTB = ROWS * 2 * S::PAD;
+  constexpr int FFTB = ROWS * fft_team_lds<L>();
   constexpr int SH = (2 * TILE > FFTB) ? 2 * TILE : FFTB;
   __shared__ float2 tw[L];
   __shared__ float2 sh[SH];
@@ -132,8 +142,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     val[e] = (n < N && p < N) ? Dt[team * N + p] : make_float2(0.f, 0.f);
   }
   __syncthreads();  // LDS tiles are reused as FFT buffers below
-  float2* b0 = sh + team * 2 * S::PAD;
-  fft_team<L, false, true>(val, t, b0, b0 + S::PAD, tw);
+  fft_team<L, false, true>(val, t, team_buf0<L>(sh, team), team_buf1<L>(sh, team), tw);
   if (n < N) {
     float2* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
@@ -149,51 +158,93 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 }
 
 // ---------------------------------------------------------------- column pass
-template <int L, int COLS>
-__global__ __launch_bounds__(256) void k_colpass(int N, float2* __restrict__ T,
-                                                 const float* __restrict__ khat_s,
-                                                 const float2* __restrict__ twg) {
+// Block = COLS columns of frame f, THREADS threads (TEAMS = THREADS / (L/8)
+// columns transformed at once).  With p3 != NULL the block also writes the
+// partial sum over its columns of khat_s |FFT(pad col)|^2, which by Parseval
+// is its share of Re<v, Q v>.
+template <int L>
+struct ColCfg {
+  static constexpr int T = L / 8;
+  static constexpr int THREADS = (L == 512) ? 512 : 256;
+  static constexpr int TEAMS = THREADS / T;
+  static constexpr int COLS = (L <= 64) ? 32 : (L <= 512 ? 16 : 8);
+  static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
+};
+
+template <int L>
+__global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* __restrict__ T,
+                                                               const float* __restrict__ khat_s,
+                                                               double* __restrict__ p3,
+                                                               const float2* __restrict__ twg) {
   using S = FftShape<L>;
-  constexpr int TEAMS = 256 / S::T;
-  static_assert(COLS % TEAMS == 0, "columns per block must be a multiple of teams");
+  using C = ColCfg<L>;
+  constexpr int COLS = C::COLS;
+  constexpr int TEAMS = C::TEAMS;
+  constexpr int NT = C::THREADS;
+  // Column-major tile: column c at tile[c * TS + n].  TS = L/2 + 4 makes the
+  // column stride 8 words mod 64 banks, so both the row-wise global staging
+  // (consecutive threads -> consecutive columns) and the column-wise FFT
+  // gathers (consecutive threads -> consecutive rows) are conflict-free.
+  constexpr int TS = L / 2 + 4;
   __shared__ float2 tw[L];
-  __shared__ float2 tile[(L / 2) * COLS];
-  __shared__ float2 bufs[TEAMS][2][S::PAD];
+  __shared__ float2 tile[COLS * TS];
+  __shared__ float2 bufs[TEAMS * fft_team_lds<L>()];
+  __shared__ double red[NT / 64];
   const int f = blockIdx.y;
   const int q0 = blockIdx.x * COLS;
   float2* Tf = T + (size_t)f * N * L;
+  double dqd = 0.0;
   load_twiddles<L>(tw, twg);
-  for (int i = threadIdx.x; i < N * COLS; i += 256) {
+  for (int i = threadIdx.x; i < N * COLS; i += NT) {
     const int n = i / COLS, c = i - n * COLS;
-    tile[i] = Tf[(size_t)n * L + q0 + c];
+    tile[c * TS + n] = Tf[(size_t)n * L + q0 + c];
   }
   __syncthreads();
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  float2* b0 = team_buf0<L>(bufs, team);
+  float2* b1 = team_buf1<L>(bufs, team);
+  // Wave-local teams touch only their own columns and buffers: no block
+  // barrier inside the loop.  Multi-wave teams synchronise inside the FFT.
 #pragma unroll 1
   for (int c0 = 0; c0 < COLS; c0 += TEAMS) {
     const int c = c0 + team;
+    const bool active = c < COLS;  // uniform per team
     float2 val[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int p = t + e * S::T;
-      val[e] = (p < N) ? tile[p * COLS + c] : make_float2(0.f, 0.f);
+      val[e] = (active && p < N) ? tile[c * TS + p] : make_float2(0.f, 0.f);
     }
-    fft_team<L, false, true>(val, t, bufs[team][0], bufs[team][1], tw);
-    const float* kq = khat_s + (size_t)(q0 + c) * L;
+    fft_team<L, false, true>(val, t, b0, b1, tw);
+    const float* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
+    float acc = 0.f;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) val[e] = c_scale(val[e], kq[t + e * S::T]);
-    __syncthreads();
-    fft_team<L, true, false>(val, t, bufs[team][0], bufs[team][1], tw);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int p = t + e * S::T;
-      if (p < N) tile[p * COLS + c] = val[e];
+    for (int e = 0; e < 8; ++e) {
+      const float kv = kq[t + e * S::T];
+      acc = fmaf(kv, c_abs2(val[e]), acc);
+      val[e] = c_scale(val[e], kv);
     }
-    __syncthreads();
+    if (active) dqd += (double)acc;
+    if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
+    fft_team<L, true, false>(val, t, b0, b1, tw);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = t + e * S::T;
+        if (p < N) tile[c * TS + p] = val[e];
+      }
+    }
+    if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
   }
-  for (int i = threadIdx.x; i < N * COLS; i += 256) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < N * COLS; i += NT) {
     const int n = i / COLS, c = i - n * COLS;
-    Tf[(size_t)n * L + q0 + c] = tile[i];
+    Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
+  }
+  if (p3) {
+    double v1[1] = {dqd};
+    block_sum<1>(v1, red);
+    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + blockIdx.x] = v1[0];
   }
 }
 
@@ -201,14 +252,11 @@ __global__ __launch_bounds__(256) void k_colpass(int N, float2* __restrict__ T,
 template <int L>
 __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict__ T,
                                                  float2* __restrict__ out,
-                                                 const float2* __restrict__ d,
-                                                 double* __restrict__ p3,
                                                  const float2* __restrict__ twg) {
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   __shared__ float2 tw[L];
-  __shared__ float2 bufs[ROWS][2][S::PAD];
-  __shared__ double red[4];
+  __shared__ float2 bufs[ROWS * fft_team_lds<L>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
@@ -218,26 +266,14 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict
 #pragma unroll
   for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft_team<L, true, false>(val, t, bufs[team][0], bufs[team][1], tw);
-  double acc = 0.0;
+  fft_team<L, true, false>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
   if (n < N) {
     const size_t ro = ((size_t)f * N + n) * N;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int p = t + e * S::T;
-      if (p < N) {
-        out[ro + p] = val[e];
-        if (d) {
-          const float2 dv = d[ro + p];
-          acc += (double)dv.x * (double)val[e].x + (double)dv.y * (double)val[e].y;
-        }
-      }
+      if (p < N) out[ro + p] = val[e];
     }
-  }
-  if (d) {
-    double v1[1] = {acc};
-    block_sum<1>(v1, red);
-    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + blockIdx.x] = v1[0];
   }
 }
 
@@ -253,6 +289,18 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict
     default: return hipErrorInvalidValue;                \
   }
 
+int fft_cols_per_block(int L) {
+  switch (L) {
+    case 64: return ColCfg<64>::COLS;
+    case 128: return ColCfg<128>::COLS;
+    case 256: return ColCfg<256>::COLS;
+    case 512: return ColCfg<512>::COLS;
+    case 1024: return ColCfg<1024>::COLS;
+    case 2048: return ColCfg<2048>::COLS;
+    default: return 1;
+  }
+}
+
 hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
                                const float2* tw, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
@@ -260,26 +308,17 @@ hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
   return hipGetLastError();
 }
 
-hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s,
+hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
                           const float2* tw, hipStream_t s) {
   dim3 grid(L / fft_cols_per_block(L), B);
-  switch (L) {
-    case 64: k_colpass<64, 32><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    case 128: k_colpass<128, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    case 256: k_colpass<256, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    case 512: k_colpass<512, 16><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    case 1024: k_colpass<1024, 8><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    case 2048: k_colpass<2048, 8><<<grid, 256, 0, s>>>(N, T, khat_s, tw); break;
-    default: return hipErrorInvalidValue;
-  }
+  RECON_L_SWITCH(L, (k_colpass<LL><<<grid, ColCfg<LL>::THREADS, 0, s>>>(N, T, khat_s, p3, tw)));
   return hipGetLastError();
 }
 
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
-                          const float2* d, double* p3, const float2* tw,
-                          hipStream_t s) {
+                          const float2* tw, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, d, p3, tw)));
+  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, tw)));
   return hipGetLastError();
 }
 
