@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 import synthetic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+PRECS = {"fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
 METRIC = "recons/sec + p50/p99 latency at 256^2 spiral, rel-L2<=1e-4 vs FP64 oracle"
 
 
@@ -94,7 +95,7 @@ def cpu_baseline(args, torch, recon, prec):
     return dict(value=1.0 / dt, unit="recons/sec", cores=int(threads), kind="oracle",
                 sample=(f"one 256x256 frame, M={prob.M}: adjoint + Gram kernel + "
                         f"{prob.iters} iterations in FP64 numpy ({dt:.1f} s)"),
-                seconds=dt), rel
+                seconds=dt), rel, (y[0], xo)
 
 
 def main():
@@ -106,8 +107,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--trace", default="colpass",
                     choices=["colpass", "dir_rowfft", "rowifft", "update"])
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"],
-                    help="adjoint contraction precision (fp64: FP64 MFMA accumulation)")
+    ap.add_argument("--prec", default="fp64", choices=list(PRECS),
+                    help="NUDFT contraction precision (fp64: FP64-accumulated adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=10)
     args = ap.parse_args()
@@ -130,7 +131,7 @@ def main():
 
     # device-resident inputs and buffers (allocated once)
     lib = recon.load()
-    prec = recon.FP64 if args.prec == "fp64" else recon.FP32
+    prec = PRECS[args.prec]
     plan = recon.Plan(prob.k, N, L, prec=prec)
     plan.gram_kernel()
     y = synth_batch(plan, prob, B, torch)
@@ -216,8 +217,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("fp32 iterations; fp64 adjoint and Gram accumulation, fp64 reductions"
-                  if args.prec == "fp64" else "fp32 (fp64 Gram accumulation and reductions)"),
+        "dtype": {"fp64": "fp32 iterations; fp64-accumulated adjoint, fp64 Gram and reductions",
+                  "fp32": "fp32 (fp64 Gram accumulation and reductions)",
+                  "fp16x3": "fp32 iterations; fp16 hi+lo split NUDFT, fp64 Gram and reductions",
+                  "bf16x3": "fp32 iterations; bf16 hi+lo split NUDFT, fp64 Gram and reductions"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"256x256 spiral M={M} (16 interleaves, 2x angular "
                                f"undersampling), hyperbolic delta={prob.delta}, "
@@ -234,9 +237,10 @@ def main():
         "status_ok_frames": int(np.sum(st["status"] == 0)),
         "grad_ratio_median": float(np.median(st["grad_ratio"])),
     }
+    oracle_frame = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle, one frame)")
-        cb, rel = cpu_baseline(args, torch, recon, prec)
+        cb, rel, oracle_frame = cpu_baseline(args, torch, recon, prec)
         out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
         out["rel_l2_vs_oracle_one_frame"] = rel
     print(json.dumps(out), flush=True)

@@ -75,7 +75,7 @@ typedef enum {
   RECON_FP16X3 = 2,       /* split fp16 hi+lo operands, 3 products, FP32 acc. */
   RECON_FP64 = 3          /* adjoint with FP64 phasors, products and MFMA
                              accumulation, rounded to FP32 once (accurate
-                             form; forward stays FP32) */
+                             form); the forward model stays FP32 */
 } recon_prec_t;
 
 /* Penalty phi(s), s = |difference| (Section 3.3). */

@@ -57,11 +57,10 @@ recon_status_t check_geometry(int64_t M, int32_t N, int32_t L) {
 }
 
 struct PlanLayout {
-  size_t k, ex, ey, tw, khat, total;
+  size_t k, ex, ey, tw, khat, at, xs, total;
 };
 
 PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
-  (void)prec;
   PlanLayout p{};
   size_t off = 0;
   p.k = off;
@@ -74,12 +73,19 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
   off = align_up(off + (size_t)L * sizeof(float2));
   p.khat = off;
   off = align_up(off + (size_t)L * L * sizeof(float));
+  p.at = p.xs = 0;
+  if (prec == RECON_BF16X3 || prec == RECON_FP16X3) {
+    p.at = off;
+    off = align_up(off + 4 * (size_t)N * split_pad_M(M) * 2);
+    p.xs = off;
+    off = align_up(off + 4 * (size_t)M * split_pad_N(N) * 2);
+  }
   p.total = off;
   return p;
 }
 
 struct WsLayout {
-  size_t b, x[2], r, g, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, adj, total;
+  size_t b, x[2], r, g, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, sc, adj, total;
   int nb1, nb3, nb4, adj_splits;
 };
 
@@ -111,6 +117,7 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   w.pobj = take((size_t)B * w.nb4 * 3 * sizeof(double));
   w.params = take((size_t)B * sizeof(FrameParam));
   w.yy = take((size_t)B * sizeof(double));
+  w.sc = take((size_t)B * sizeof(float));
   w.adj_splits = adjoint_splits(M, N);
   {
     const int g = adjoint_group(M, N);
@@ -192,6 +199,11 @@ struct recon_plan_s {
   float2* ey() const { return reinterpret_cast<float2*>(mem + lay.ey); }
   float2* tw() const { return reinterpret_cast<float2*>(mem + lay.tw); }
   float* khat() const { return reinterpret_cast<float*>(mem + lay.khat); }
+  void* at() const { return mem + lay.at; }
+  void* xs() const { return mem + lay.xs; }
+  bool split() const { return prec == RECON_BF16X3 || prec == RECON_FP16X3; }
+  int table_prec() const { return prec; }
+  bool has_tables() const { return split(); }
 };
 
 namespace {
@@ -232,9 +244,12 @@ recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, f
 }
 
 recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b, void* part,
-                              hipStream_t s) {
+                              float* sc, hipStream_t s) {
   TraceScope ts(TK_ADJ, s);
-  if (p->prec == RECON_FP64)
+  if (p->split())
+    HIP_TRY(launch_adjoint_split(p->prec, p->M, p->N, B, p->at(), p->ex(), y, sc, b,
+                                 static_cast<float2*>(part), s));
+  else if (p->prec == RECON_FP64)
     HIP_TRY(launch_adjoint_f64(p->M, p->N, B, p->k(), y, b, static_cast<double2*>(part), s));
   else
     HIP_TRY(launch_adjoint_f32(p->M, p->N, B, p->ex(), p->ey(), y, b, static_cast<float2*>(part), s));
@@ -272,11 +287,7 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   if (L == 0) L = default_L(N);
   recon_status_t st = check_geometry(M, N, L);
   if (st != RECON_OK) return st;
-  if (prec != RECON_FP32 && prec != RECON_FP64) {
-    if (prec == RECON_BF16X3 || prec == RECON_FP16X3)
-      return fail(RECON_E_RANGE, "split precisions are not available in this build");
-    return fail(RECON_E_ARG, "unknown precision");
-  }
+  if (prec < RECON_FP32 || prec > RECON_FP64) return fail(RECON_E_ARG, "unknown precision");
   for (int64_t i = 0; i < 2 * M; ++i) {
     const double v = traj[i];
     if (!std::isfinite(v) || std::fabs(v) > 0.5)
@@ -303,6 +314,8 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->tw(), tw.data(), (size_t)L * sizeof(float2), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_tables_f32(M, N, p->k(), p->ex(), p->ey(), s);
+  if (e == hipSuccess && p->has_tables())
+    e = launch_tables_split(p->table_prec(), M, N, p->k(), p->at(), p->xs(), s);
   // The host copies above read caller and local memory: finish before return.
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -355,19 +368,26 @@ recon_status_t recon_adjoint(recon_plan_t p, const float* y, int32_t B, float* b
   hipStream_t s = as_stream(stream);
   const float2* y2 = reinterpret_cast<const float2*>(y);
   if (yy_out) HIP_TRY(launch_sumsq(p->M, B, y2, yy_out, s));
-  return adjoint_traced(p, y2, B, reinterpret_cast<float2*>(b), w.img(w.lay.adj), s);
+  return adjoint_traced(p, y2, B, reinterpret_cast<float2*>(b), w.img(w.lay.adj),
+                        reinterpret_cast<float*>(w.base + w.lay.sc), s);
 }
 
 recon_status_t recon_forward(recon_plan_t p, const float* x, int32_t B, float* y, void* ws,
                              size_t ws_bytes, void* stream) {
   g_last_error.clear();
   if (!p || !x || !y) return fail(RECON_E_ARG, "NULL argument");
-  (void)ws;
-  (void)ws_bytes;
-  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  Ws w;
+  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st != RECON_OK) return st;
   TraceScope ts(TK_FWD, as_stream(stream));
-  HIP_TRY(launch_forward_f32(p->M, p->N, B, p->ex(), p->ey(), reinterpret_cast<const float2*>(x),
-                             reinterpret_cast<float2*>(y), as_stream(stream)));
+  if (p->has_tables())
+    HIP_TRY(launch_forward_split(p->table_prec(), p->M, p->N, B, p->xs(), p->ey(),
+                                 reinterpret_cast<const float2*>(x),
+                                 reinterpret_cast<float*>(w.base + w.lay.sc),
+                                 reinterpret_cast<float2*>(y), as_stream(stream)));
+  else
+    HIP_TRY(launch_forward_f32(p->M, p->N, B, p->ex(), p->ey(), reinterpret_cast<const float2*>(x),
+                               reinterpret_cast<float2*>(y), as_stream(stream)));
   return RECON_OK;
 }
 
@@ -405,7 +425,8 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   if (y) {
     const float2* y2 = reinterpret_cast<const float2*>(y);
     HIP_TRY(launch_sumsq(p->M, B, y2, yy, s));
-    recon_status_t r = adjoint_traced(p, y2, B, b, w.img(w.lay.adj), s);
+    recon_status_t r = adjoint_traced(p, y2, B, b, w.img(w.lay.adj),
+                                      reinterpret_cast<float*>(w.base + w.lay.sc), s);
     if (r != RECON_OK) return r;
   } else {
     HIP_TRY(hipMemcpyAsync(b, b_in, (size_t)B * N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));

@@ -6,6 +6,10 @@
 
 namespace recon {
 
+// Operand precisions of the split NUDFT contractions (values of recon_prec_t).
+constexpr int RECON_PREC_BF16X3 = 1;
+constexpr int RECON_PREC_FP16X3 = 2;
+
 // Per-frame penalty parameters (device array, one entry per frame).
 struct FrameParam {
   float lam;
@@ -97,6 +101,22 @@ hipError_t launch_forward_f32(int64_t M, int N, int B, const float2* ex,
                               hipStream_t s);
 hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* yy,
                         hipStream_t s);
+
+// ---- split-precision NUDFT (BF16 x3 / FP16 x3) ------------------------------
+// Padded table geometry (multiples of the 32-wide MFMA k-step).
+int64_t split_pad_M(int64_t M);
+int split_pad_N(int N);
+// at: [4][N][Mp] 16-bit (hi/lo of Re Ey, hi/lo of -Im Ey, l contiguous);
+// xs: [4][M][Np] 16-bit (hi/lo of Re Ex, hi/lo of Im Ex, m contiguous).
+hipError_t launch_tables_split(int prec, int64_t M, int N, const double* k, void* at, void* xs,
+                               hipStream_t s);
+// sc: per-frame scale scratch [B]; part: split-K partials [splits][group][N][N].
+hipError_t launch_adjoint_split(int prec, int64_t M, int N, int B, const void* at,
+                                const float2* ex, const float2* y, float* sc, float2* b,
+                                float2* part, hipStream_t s);
+hipError_t launch_forward_split(int prec, int64_t M, int N, int B, const void* xs,
+                                const float2* ey, const float2* x, float* sc, float2* y,
+                                hipStream_t s);
 
 // ---- Gram kernel (Eq. DG, FP64) ----------------------------------------------
 int gram_splits(int64_t M, int N);

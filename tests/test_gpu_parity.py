@@ -288,3 +288,47 @@ def test_end_to_end_plain_workload(prec, bound):
           f"{h['J'][-1]:.9g}; grad ratio {st['grad_ratio'][0]:.3e} vs {h['gnorm'][-1] / h['gnorm'][0]:.3e}")
     assert e < bound
     assert abs(st["J"][0] - h["J"][-1]) < 1e-5 * abs(h["J"][-1])
+
+
+# Split-precision NUDFT (the precision form).  Each real product is
+# a_hi b_hi + a_hi b_lo + a_lo b_hi of bf16 (8-bit significands, ~16-bit pairs)
+# or fp16 (11-bit, ~22-bit pairs) parts with FP32 accumulation: expected
+# relative errors ~1e-5 (bf16) and ~3e-7 (fp16, phasor parts carry absolute
+# error <= 2^-25).
+SPLIT_TOL = {recon.BF16X3: 1e-5, recon.FP16X3: 1e-6}
+
+
+@pytest.mark.parametrize("prec", [recon.BF16X3, recon.FP16X3])
+@pytest.mark.parametrize("name,N,karg,B", CASES + [("n256", 256, (16, 2048, 2.0), 2)])
+def test_split_precision_adjoint_and_forward(name, N, karg, B, prec):
+    rng = np.random.default_rng(abs(hash(name)) % 2**31 + 7)
+    k = spiral(N, *karg)
+    plan = recon.Plan(k, N, prec=prec)
+    y = (3.7 * rand_c(rng, B, k.shape[0])).astype(np.complex64)  # scaling exercised
+    b_ref = oracle.adjoint(y, k, N)
+    b = host(plan.adjoint(dev(y)))
+    x = (0.3 * rand_c(rng, B, N, N)).astype(np.complex64)
+    y_ref = oracle.forward(x, k)
+    yg = host(plan.forward(dev(x)))
+    eb, ey = rel(b, b_ref), rel(yg, y_ref)
+    per_frame = [rel(b[f], b_ref[f]) for f in range(B)]
+    print(f"{name} prec={prec}: adjoint rel {eb:.2e} (frames {max(per_frame):.2e}), "
+          f"forward rel {ey:.2e}")
+    assert eb < SPLIT_TOL[prec] and max(per_frame) < SPLIT_TOL[prec]
+    assert ey < SPLIT_TOL[prec]
+
+
+@pytest.mark.parametrize("prec,bound", [(recon.BF16X3, 5e-5), (recon.FP16X3, 1e-5)])
+def test_split_precision_end_to_end_tiny(prec, bound):
+    """The converged 32x32 workload with the split adjoint: the iterate's
+    error tracks the adjoint's (amplified by the conditioning)."""
+    p, y = _c1_inputs()
+    plan = recon.Plan(p.k, p.N, p.L, prec=prec)
+    plan.gram_kernel()
+    x, st = plan.solve(dev(y), p.lam, p.delta, p.iters)
+    b = oracle.adjoint(y[0].astype(np.complex64), p.k, p.N)
+    K = oracle.khat(p.k, p.N, p.L)
+    xo = oracle.solve(b, K, p.lam, p.delta, p.iters)
+    e = rel(host(x)[0], xo)
+    print(f"C1 end-to-end prec={prec}: rel {e:.3e}")
+    assert e < bound
