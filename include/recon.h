@@ -205,6 +205,47 @@ recon_status_t recon_solve_end(recon_plan_t plan, float* x_out,
 recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
                                   void* ws, size_t ws_bytes, void* stream);
 
+/* ---- slot pools: continuous batching of independent frames ------------- */
+
+/* A slot pool is a workspace sized for B frames (recon_workspace_bytes(B))
+ * whose frames ("slots") start and finish at different times.  All slots
+ * share one plan (trajectory, N, L) and one penalty kind; lambda, delta and
+ * the iteration budget are per slot.  Every iteration kernel runs on all B
+ * slots of the pool and skips, as a whole block, the slots that are idle or
+ * already done, so a frame that joins the pool at any iteration follows
+ * exactly the sequence of operations of recon_solve with B = 1 and x0 = 0
+ * (Section 3.3 of the paper): its result is bitwise equal to that solve.
+ *
+ *   recon_pool_reset:  bind the workspace to a pool of B idle slots.
+ *   recon_pool_admit:  start a frame in an idle (or retired) slot: ||y||^2,
+ *                      b = A^H y and the initial state, with a budget of
+ *                      `iters` iterations from the pool's current iteration
+ *                      counter.  y: device complex64 [M] (the plan's sample
+ *                      order).  RECON_E_STATE if the slot is still running.
+ *   recon_pool_step:   run `iters` iterations of the pool (all running slots
+ *                      advance; slots whose budget is used up stay frozen).
+ *   recon_pool_retire: objective/stats of a finished slot (stats: device
+ *                      recon_stats_t, may be NULL) and a copy of its image
+ *                      to x_out (device complex64 [N][N], may be NULL).
+ *                      RECON_E_STATE while the slot still has iterations
+ *                      left.  The slot is idle afterwards.
+ *   recon_pool_iteration: the pool's iteration counter (iterations run by
+ *                      recon_pool_step since the reset), -1 on error.
+ * All calls are stream-ordered on `stream`; calls on one pool must not
+ * overlap (host-side state is updated at call time).  recon_solve_iterate,
+ * recon_solve_end and recon_solve_export reject a pool workspace. */
+recon_status_t recon_pool_reset(recon_plan_t plan, int32_t B, int32_t phi,
+                                void* ws, size_t ws_bytes, void* stream);
+recon_status_t recon_pool_admit(recon_plan_t plan, int32_t slot, const float* y,
+                                float lambda, float delta, int32_t iters,
+                                void* ws, size_t ws_bytes, void* stream);
+recon_status_t recon_pool_step(recon_plan_t plan, int32_t iters, void* ws,
+                               size_t ws_bytes, void* stream);
+recon_status_t recon_pool_retire(recon_plan_t plan, int32_t slot, float* x_out,
+                                 recon_stats_t* stats, void* ws,
+                                 size_t ws_bytes, void* stream);
+int64_t recon_pool_iteration(recon_plan_t plan, void* ws);
+
 /* ---- diagnostics -------------------------------------------------------- */
 
 /* Kernel timing trace (HIP events around every launch of one kernel kind on

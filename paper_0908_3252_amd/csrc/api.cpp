@@ -178,8 +178,11 @@ enum { TK_DIR = 0, TK_COL = 1, TK_ROWINV = 2, TK_UPDATE = 3, TK_ADJ = 4, TK_GRAM
 struct SolveCtx {
   int B = 0;
   int phi = 0;
-  int iters = 0;
+  int iters = 0;                 // iterations run so far on this workspace (k)
   bool has_y = false;
+  bool pool = false;             // slot pool of the serving path
+  std::vector<int32_t> start_at;  // per slot (pool only): k at admission
+  std::vector<int32_t> stop_at;   // per slot (pool only): k at which the slot stops
 };
 
 }  // namespace
@@ -234,11 +237,11 @@ recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, f
   HIP_TRY(launch_rowfft_plain(p->L, p->N, B, v, T, p->tw(), s));
   {
     TraceScope ts(TK_COL, s);
-    HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat(), p3, p->tw(), s));
+    HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat(), p3, p->tw(), nullptr, 0, s));
   }
   {
     TraceScope ts(TK_ROWINV, s);
-    HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, p->tw(), s));
+    HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, p->tw(), nullptr, 0, s));
   }
   return RECON_OK;
 }
@@ -432,7 +435,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
     HIP_TRY(hipMemcpyAsync(b, b_in, (size_t)B * N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_zero_f64((size_t)B, yy, s));
   }
-  HIP_TRY(launch_set_params(B, lambda, delta, w.params(), s));
+  HIP_TRY(launch_set_params(B, lambda, delta, INT32_MAX, w.params(), s));
   const float2* qx0 = nullptr;
   if (x0) {
     recon_status_t r = gram_apply(p, reinterpret_cast<const float2*>(x0), w.img(w.lay.qd), B,
@@ -445,6 +448,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
                       w.dbl(w.lay.pg0), w.params(), s));
   std::lock_guard<std::mutex> lk(p->mu);
   SolveCtx& c = p->solves[ws];
+  c = SolveCtx{};
   c.B = B;
   c.phi = phi;
   c.iters = 0;
@@ -460,22 +464,14 @@ static recon_status_t get_ctx(recon_plan_t p, void* ws, SolveCtx* out) {
   return RECON_OK;
 }
 
-recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size_t ws_bytes,
-                                   void* stream) {
-  g_last_error.clear();
-  if (!p) return fail(RECON_E_ARG, "NULL plan");
-  if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
-  SolveCtx c;
-  recon_status_t st = get_ctx(p, ws, &c);
-  if (st != RECON_OK) return st;
-  Ws w;
-  st = check_ws(p, ws, ws_bytes, c.B, &w);
-  if (st != RECON_OK) return st;
-  hipStream_t s = as_stream(stream);
+// Iterations k0 .. k0+iters-1 of the pseudo-conjugate gradient on every frame
+// of the workspace (frames with stop_at <= k are skipped by the kernels).
+static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
+                                     int iters, hipStream_t s) {
   const int N = p->N, L = p->L, B = c.B;
   float2* T = w.img(w.lay.T);
   for (int it = 0; it < iters; ++it) {
-    const int k = c.iters + it;
+    const int k = k0 + it;
     float2* d_old = w.img(w.lay.d[k & 1]);
     float2* d_new = w.img(w.lay.d[(k + 1) & 1]);
     float2* x_old = w.img(w.lay.x[k & 1]);
@@ -484,23 +480,40 @@ recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size
       TraceScope ts(TK_DIR, s);
       HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, w.img(w.lay.g), d_old, d_new, x_old, T,
                                 w.dbl(w.lay.p4), w.lay.nb4, w.dbl(w.lay.p1), w.params(), p->tw(),
-                                s));
+                                k, s));
     }
     {
       TraceScope ts(TK_COL, s);
-      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), w.dbl(w.lay.p3), p->tw(), s));
+      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), w.dbl(w.lay.p3), p->tw(), w.params(), k, s));
     }
     {
       TraceScope ts(TK_ROWINV, s);
-      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), p->tw(), s));
+      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), p->tw(), w.params(), k, s));
     }
     {
       TraceScope ts(TK_UPDATE, s);
       HIP_TRY(launch_update(c.phi, N, B, x_old, x_new, d_new, w.img(w.lay.r), w.img(w.lay.qd),
                             w.img(w.lay.g), w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3),
-                            w.lay.nb3, w.dbl(w.lay.p4), w.params(), s));
+                            w.lay.nb3, w.dbl(w.lay.p4), w.params(), k, s));
     }
   }
+  return RECON_OK;
+}
+
+recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
+  SolveCtx c;
+  recon_status_t st = get_ctx(p, ws, &c);
+  if (st != RECON_OK) return st;
+  if (c.pool) return fail(RECON_E_STATE, "workspace is a slot pool: use recon_pool_step");
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  st = run_iterations(p, c, w, c.iters, iters, as_stream(stream));
+  if (st != RECON_OK) return st;
   std::lock_guard<std::mutex> lk(p->mu);
   p->solves[ws].iters = c.iters + iters;
   return RECON_OK;
@@ -513,6 +526,7 @@ recon_status_t recon_solve_export(recon_plan_t p, int32_t field, float* out, voi
   SolveCtx c;
   recon_status_t st = get_ctx(p, ws, &c);
   if (st != RECON_OK) return st;
+  if (c.pool) return fail(RECON_E_STATE, "workspace is a slot pool: use recon_pool_retire");
   Ws w;
   st = check_ws(p, ws, ws_bytes, c.B, &w);
   if (st != RECON_OK) return st;
@@ -541,6 +555,7 @@ recon_status_t recon_solve_end(recon_plan_t p, float* x_out, recon_stats_t* stat
   SolveCtx c;
   recon_status_t st = get_ctx(p, ws, &c);
   if (st != RECON_OK) return st;
+  if (c.pool) return fail(RECON_E_STATE, "workspace is a slot pool: use recon_pool_retire");
   Ws w;
   st = check_ws(p, ws, ws_bytes, c.B, &w);
   if (st != RECON_OK) return st;
@@ -570,6 +585,131 @@ recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, float lamb
   st = recon_solve_iterate(p, iters, ws, ws_bytes, stream);
   if (st != RECON_OK) return st;
   return recon_solve_end(p, x, stats, ws, ws_bytes, stream);
+}
+
+// ---- slot pools (continuous batching) -------------------------------------
+
+recon_status_t recon_pool_reset(recon_plan_t p, int32_t B, int32_t phi, void* ws, size_t ws_bytes,
+                                void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
+  if (phi < 0 || phi > 2) return fail(RECON_E_ARG, "unknown penalty");
+  Ws w;
+  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st != RECON_OK) return st;
+  // every slot idle: stop_at = 0
+  HIP_TRY(launch_set_params(B, 0.f, 1.f, 0, w.params(), as_stream(stream)));
+  std::lock_guard<std::mutex> lk(p->mu);
+  SolveCtx& c = p->solves[ws];
+  c = SolveCtx{};
+  c.B = B;
+  c.phi = phi;
+  c.iters = 0;
+  c.pool = true;
+  c.start_at.assign(B, 0);
+  c.stop_at.assign(B, 0);
+  return RECON_OK;
+}
+
+static recon_status_t get_pool(recon_plan_t p, void* ws, SolveCtx* out) {
+  recon_status_t st = get_ctx(p, ws, out);
+  if (st != RECON_OK) return st;
+  if (!out->pool) return fail(RECON_E_STATE, "workspace is not a slot pool (recon_pool_reset)");
+  return RECON_OK;
+}
+
+recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, float lambda,
+                                float delta, int32_t iters, void* ws, size_t ws_bytes,
+                                void* stream) {
+  g_last_error.clear();
+  if (!p || !y) return fail(RECON_E_ARG, "NULL argument");
+  SolveCtx c;
+  recon_status_t st = get_pool(p, ws, &c);
+  if (st != RECON_OK) return st;
+  if (slot < 0 || slot >= c.B) return fail(RECON_E_RANGE, "slot out of range");
+  if (c.stop_at[slot] > c.iters) return fail(RECON_E_STATE, "slot is busy");
+  if (iters < 0 || (int64_t)c.iters + iters > INT32_MAX) return fail(RECON_E_RANGE, "bad iteration count");
+  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
+  if (c.phi != RECON_PHI_QUADRATIC && (!(delta > 0.f) || !std::isfinite(delta)))
+    return fail(RECON_E_RANGE, "delta must be > 0");
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const int N = p->N;
+  const size_t fo = (size_t)slot * N * N;
+  const int k = c.iters;
+  const float2* y2 = reinterpret_cast<const float2*>(y);
+  HIP_TRY(launch_sumsq(p->M, 1, y2, w.dbl(w.lay.yy) + slot, s));
+  st = adjoint_traced(p, y2, 1, w.img(w.lay.b) + fo, w.img(w.lay.adj),
+                      reinterpret_cast<float*>(w.base + w.lay.sc) + slot, s);
+  if (st != RECON_OK) return st;
+  const int stop = k + iters;
+  HIP_TRY(launch_set_params(1, lambda, delta, stop, w.params() + slot, s));
+  HIP_TRY(launch_init(c.phi, N, 1, w.img(w.lay.b) + fo, nullptr, nullptr,
+                      w.img(w.lay.x[k & 1]) + fo, w.img(w.lay.r) + fo, w.img(w.lay.g) + fo,
+                      w.img(w.lay.d[k & 1]) + fo, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
+                      w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.params() + slot, s));
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->solves[ws].start_at[slot] = k;
+  p->solves[ws].stop_at[slot] = stop;
+  return RECON_OK;
+}
+
+recon_status_t recon_pool_step(recon_plan_t p, int32_t iters, void* ws, size_t ws_bytes,
+                               void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
+  SolveCtx c;
+  recon_status_t st = get_pool(p, ws, &c);
+  if (st != RECON_OK) return st;
+  if ((int64_t)c.iters + iters > INT32_MAX) return fail(RECON_E_RANGE, "iteration counter overflow");
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  st = run_iterations(p, c, w, c.iters, iters, as_stream(stream));
+  if (st != RECON_OK) return st;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->solves[ws].iters = c.iters + iters;
+  return RECON_OK;
+}
+
+recon_status_t recon_pool_retire(recon_plan_t p, int32_t slot, float* x_out, recon_stats_t* stats,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  SolveCtx c;
+  recon_status_t st = get_pool(p, ws, &c);
+  if (st != RECON_OK) return st;
+  if (slot < 0 || slot >= c.B) return fail(RECON_E_RANGE, "slot out of range");
+  const int stop = c.stop_at[slot];
+  if (stop > c.iters) return fail(RECON_E_STATE, "slot has not finished its iterations");
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w);
+  if (st != RECON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  const int N = p->N;
+  const size_t fo = (size_t)slot * N * N;
+  float2* x = w.img(w.lay.x[stop & 1]) + fo;
+  if (stats) {
+    double* pobj = w.dbl(w.lay.pobj) + (size_t)slot * w.lay.nb4 * 3;
+    HIP_TRY(launch_objective(c.phi, N, 1, x, w.img(w.lay.b) + fo, w.img(w.lay.r) + fo, pobj,
+                             w.params() + slot, s));
+    HIP_TRY(launch_stats(1, pobj, w.lay.nb4, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
+                         w.lay.nb4, w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.lay.nb4,
+                         w.dbl(w.lay.yy) + slot, stop - c.start_at[slot], w.params() + slot,
+                         stats, s));
+  }
+  if (x_out) HIP_TRY(hipMemcpyAsync(x_out, x, (size_t)N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
+  return RECON_OK;
+}
+
+int64_t recon_pool_iteration(recon_plan_t p, void* ws) {
+  SolveCtx c;
+  if (!p || get_ctx(p, ws, &c) != RECON_OK) return -1;
+  return c.iters;
 }
 
 recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity) {

@@ -24,9 +24,9 @@ __global__ void k_zero_f64(size_t n, double* p) {
     p[i] = 0.0;
 }
 
-__global__ void k_set_params(int B, float lam, float delta, FrameParam* fp) {
+__global__ void k_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < B) fp[f] = FrameParam{lam, delta};
+  if (f < B) fp[f] = FrameParam{lam, delta, stop_at, 0};
 }
 
 // Rows n0-1 .. n0+ROWS of x (x_old + alpha d, or x as given) staged in LDS.
@@ -36,10 +36,11 @@ __global__ __launch_bounds__(256) void k_update(
     const float2* __restrict__ d, float2* __restrict__ r, const float2* __restrict__ qd,
     float2* __restrict__ g, const double* __restrict__ p1, int nb1,
     const double* __restrict__ p3, int nb3, double* __restrict__ p4,
-    const FrameParam* __restrict__ fp) {
+    const FrameParam* __restrict__ fp, int kit) {
   extern __shared__ float2 xt[];  // [(ROWS+2)][N]
   __shared__ double red[4 * 4];
   const int f = blockIdx.y;
+  if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
   // Step length: exact minimiser of the half-quadratic majorant along d.
@@ -248,20 +249,21 @@ hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_params(int B, float lam, float delta, FrameParam* fp, hipStream_t s) {
-  k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, fp);
+hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp,
+                             hipStream_t s) {
+  k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, stop_at, fp);
   return hipGetLastError();
 }
 
 hipError_t launch_update(int phi, int N, int B, const float2* x_old, float2* x_new,
                          const float2* d, float2* r, const float2* qd, float2* g,
                          const double* p1, int nb1, const double* p3, int nb3,
-                         double* p4, const FrameParam* fp, hipStream_t s) {
+                         double* p4, const FrameParam* fp, int k, hipStream_t s) {
   const int R = upd_rows_per_block(N);
   dim3 grid(cdiv(N, R), B);
   const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
   RECON_PHI_SWITCH(phi, (k_update<PP><<<grid, 256, shm, s>>>(N, R, x_old, x_new, d, r, qd, g,
-                                                             p1, nb1, p3, nb3, p4, fp)));
+                                                             p1, nb1, p3, nb3, p4, fp, k)));
   return hipGetLastError();
 }
 

@@ -10,10 +10,14 @@ namespace recon {
 constexpr int RECON_PREC_BF16X3 = 1;
 constexpr int RECON_PREC_FP16X3 = 2;
 
-// Per-frame penalty parameters (device array, one entry per frame).
+// Per-frame parameters (device array, one entry per frame).  A frame takes
+// part in iteration k of its workspace only while k < stop_at (slot pools of
+// the serving path; plain solves use INT32_MAX).
 struct FrameParam {
   float lam;
   float delta;
+  int32_t stop_at;
+  int32_t pad;
 };
 
 // Rows handled by one 256-thread block of the row-FFT kernels.
@@ -34,10 +38,10 @@ hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
 // p3 (optional, [B][L / cols_per_block]) receives per-block partials of
 // sum khat_s |FFT_L(col)|^2 = Re<v, Q v> (Parseval).
 hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
-                          const float2* tw, hipStream_t s);
+                          const float2* tw, const FrameParam* fp, int k, hipStream_t s);
 // Row inverse pass: out[f][n][m] = IFFT_L(T[f][n][:])[m] for m < N.
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
-                          const float2* tw, hipStream_t s);
+                          const float2* tw, const FrameParam* fp, int k, hipStream_t s);
 
 
 // ---- CG kernels (Section 3.3) -------------------------------------------------
@@ -48,14 +52,14 @@ hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
                              const float2* d_old, float2* d_new,
                              const float2* x, float2* T, const double* p4,
                              int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, hipStream_t s);
+                             const float2* tw, int k, hipStream_t s);
 // alpha from the partials; x_new = x + alpha d, r += alpha Qd,
 // g = 2 r + lam D^T(w(D x_new) D x_new); partials for beta.
 hipError_t launch_update(int phi, int N, int B, const float2* x_old,
                          float2* x_new, const float2* d, float2* r,
                          const float2* qd, float2* g, const double* p1,
                          int nb1, const double* p3, int nb3, double* p4,
-                         const FrameParam* fp, hipStream_t s);
+                         const FrameParam* fp, int k, hipStream_t s);
 // Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), g = 2r +
 // grad R(x0), d = 0; partials such that the first direction is -g.
 hipError_t launch_init(int phi, int N, int B, const float2* b,
@@ -63,7 +67,7 @@ hipError_t launch_init(int phi, int N, int B, const float2* b,
                        float2* r, float2* g, float2* d, double* p4,
                        double* pg0, const FrameParam* fp, hipStream_t s);
 hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s);
-hipError_t launch_set_params(int B, float lam, float delta, FrameParam* fp,
+hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp,
                              hipStream_t s);
 // Objective partials and final statistics.
 hipError_t launch_objective(int phi, int N, int B, const float2* x,

@@ -69,10 +69,11 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     int N, const float2* __restrict__ g, const float2* __restrict__ d_old,
     float2* __restrict__ d_new, const float2* __restrict__ x, float2* __restrict__ T,
     const double* __restrict__ p4, int nb4, double* __restrict__ p1,
-    const FrameParam* __restrict__ fp, const float2* __restrict__ twg) {
+    const FrameParam* __restrict__ fp, const float2* __restrict__ twg, int kit) {
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   constexpr int TILE = (ROWS + 1) * (L / 2);
+  if (kit >= fp[blockIdx.y].stop_at) return;  // frame idle in this iteration (block-uniform)
   constexpr int FFTB = ROWS * fft_team_lds<L>();
   constexpr int SH = (2 * TILE > FFTB) ? 2 * TILE : FFTB;
   __shared__ float2 tw[L];
@@ -175,9 +176,12 @@ template <int L>
 __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* __restrict__ T,
                                                                const float* __restrict__ khat_s,
                                                                double* __restrict__ p3,
-                                                               const float2* __restrict__ twg) {
+                                                               const float2* __restrict__ twg,
+                                                               const FrameParam* __restrict__ fp,
+                                                               int kit) {
   using S = FftShape<L>;
   using C = ColCfg<L>;
+  if (fp && kit >= fp[blockIdx.y].stop_at) return;
   constexpr int COLS = C::COLS;
   constexpr int TEAMS = C::TEAMS;
   constexpr int NT = C::THREADS;
@@ -252,9 +256,11 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* _
 template <int L>
 __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict__ T,
                                                  float2* __restrict__ out,
-                                                 const float2* __restrict__ twg) {
+                                                 const float2* __restrict__ twg,
+                                                 const FrameParam* __restrict__ fp, int kit) {
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
+  if (fp && kit >= fp[blockIdx.y].stop_at) return;
   __shared__ float2 tw[L];
   __shared__ float2 bufs[ROWS * fft_team_lds<L>()];
   const int f = blockIdx.y;
@@ -309,16 +315,17 @@ hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
 }
 
 hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
-                          const float2* tw, hipStream_t s) {
+                          const float2* tw, const FrameParam* fp, int k, hipStream_t s) {
   dim3 grid(L / fft_cols_per_block(L), B);
-  RECON_L_SWITCH(L, (k_colpass<LL><<<grid, ColCfg<LL>::THREADS, 0, s>>>(N, T, khat_s, p3, tw)));
+  RECON_L_SWITCH(L, (k_colpass<LL><<<grid, ColCfg<LL>::THREADS, 0, s>>>(N, T, khat_s, p3, tw, fp,
+                                                                        k)));
   return hipGetLastError();
 }
 
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
-                          const float2* tw, hipStream_t s) {
+                          const float2* tw, const FrameParam* fp, int k, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, tw)));
+  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, tw, fp, k)));
   return hipGetLastError();
 }
 
@@ -326,11 +333,11 @@ hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
                              const float2* d_old, float2* d_new,
                              const float2* x, float2* T, const double* p4,
                              int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, hipStream_t s) {
+                             const float2* tw, int k, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
 #define RECON_DIR(PHI_)                                                       \
   RECON_L_SWITCH(L, (k_dir_rowfft<LL, PHI_><<<grid, 256, 0, s>>>(             \
-                        N, g, d_old, d_new, x, T, p4, nb4, p1, fp, tw)))
+                        N, g, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k)))
   switch (phi) {
     case 0: RECON_DIR(0); break;
     case 1: RECON_DIR(1); break;

@@ -62,6 +62,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
         "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
         "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
+        "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
+        "recon_pool_admit": (i32, [vp, i32, vp, f32, f32, i32, vp, sz, vp]),
+        "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
+        "recon_pool_retire": (i32, [vp, i32, vp, vp, vp, sz, vp]),
+        "recon_pool_iteration": (i64, [vp, vp]),
         "recon_trace_enable": (i32, [i32, i32]),
         "recon_trace_read": (i32, [c.POINTER(c.c_float), i32]),
         "recon_status_string": (c.c_char_p, [i32]),
@@ -233,6 +238,77 @@ class Plan:
         _check(load().recon_solve_end(self._h, x.data_ptr(), st.data_ptr(), ws.data_ptr(), n,
                                       _stream()))
         return x, stats_to_numpy(st, B)
+
+
+class Pool:
+    """B reconstruction slots on one plan (continuous batching).
+
+    Frames join (admit) and leave (retire) between chunks of iterations
+    (step); each runs exactly its own iteration budget, and its result is
+    bitwise the one recon_solve gives for that frame alone.  The pool owns
+    its workspace and may run on its own stream (torch.cuda.Stream with the
+    default priority), so pools of different plans can overlap.
+    """
+
+    def __init__(self, plan: "Plan", B: int, phi: str = "hyperbolic", stream=None):
+        import torch
+        lib = load()
+        self.plan = plan
+        self.B = int(B)
+        self.phi = phi
+        self.stream = stream
+        self.nbytes = lib.recon_workspace_bytes(plan.M, plan.N, plan.L, self.B)
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            self.ws = _dev_buf(self.nbytes)
+            self.stats = _dev_buf(self.B * STATS_DTYPE.itemsize)
+        _check(lib.recon_pool_reset(plan.handle, self.B, PHI[phi], self.ws.data_ptr(),
+                                    self.nbytes, self._s()))
+
+    def _s(self):
+        return self.stream.cuda_stream if self.stream is not None else _stream()
+
+    @property
+    def iteration(self) -> int:
+        return int(load().recon_pool_iteration(self.plan.handle, self.ws.data_ptr()))
+
+    def admit(self, slot: int, y, lam: float, delta: float, iters: int):
+        """Start frame y (device complex64 [M]) in `slot` with `iters` iterations."""
+        _check(load().recon_pool_admit(self.plan.handle, int(slot), y.data_ptr(), float(lam),
+                                       float(delta), int(iters), self.ws.data_ptr(), self.nbytes,
+                                       self._s()))
+
+    def step(self, iters: int):
+        _check(load().recon_pool_step(self.plan.handle, int(iters), self.ws.data_ptr(),
+                                      self.nbytes, self._s()))
+
+    def retire(self, slot: int, x_out=None, stats: bool = True, stats_out=None):
+        """Write the finished slot's image to x_out (device complex64 [N][N])
+        and its statistics to stats_out (device buffer of STATS_DTYPE.itemsize
+        bytes) or, without one, to the pool's stats buffer (read_stats)."""
+        if stats_out is not None:
+            st = stats_out.data_ptr()
+        elif stats:
+            st = self.stats.data_ptr() + int(slot) * STATS_DTYPE.itemsize
+        else:
+            st = None
+        _check(load().recon_pool_retire(self.plan.handle, int(slot), _ptr(x_out), st,
+                                        self.ws.data_ptr(), self.nbytes, self._s()))
+
+    def read_stats(self, slots) -> np.ndarray:
+        """Statistics of retired slots (synchronises the pool's stream)."""
+        import torch
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        raw = self.stats.cpu().numpy()
+        allst = np.frombuffer(raw.tobytes(), dtype=STATS_DTYPE)
+        return allst[np.asarray(list(slots), dtype=np.int64)].copy()
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
 
 
 TRACE = {"dir_rowfft": 0, "colpass": 1, "rowifft": 2, "update": 3, "adjoint": 4, "gram": 5,

@@ -90,16 +90,24 @@ def ellipse_phantom(N: int, K: int, rng: np.random.Generator,
     if drift and drift_dirs is not None:
         cx = cx + drift * drift_dirs[:, 0]
         cy = cy + drift * drift_dirs[:, 1]
-    yy, xx = np.meshgrid(np.arange(N, dtype=np.float64),
-                         np.arange(N, dtype=np.float64), indexing="ij")
     img = np.zeros((N, N), dtype=np.complex128)
     for e in range(K):
         c, s = math.cos(rot[e]), math.sin(rot[e])
+        # Only pixels inside the ellipse's bounding box (plus a one-pixel
+        # margin) can satisfy the test; the test itself is unchanged.
+        hx = math.hypot(ax[e] * c, ay[e] * s) + 1.0
+        hy = math.hypot(ax[e] * s, ay[e] * c) + 1.0
+        m0, m1 = max(0, int(math.floor(cx[e] - hx))), min(N, int(math.ceil(cx[e] + hx)) + 1)
+        n0, n1 = max(0, int(math.floor(cy[e] - hy))), min(N, int(math.ceil(cy[e] + hy)) + 1)
+        if m0 >= m1 or n0 >= n1:
+            continue
+        yy, xx = np.meshgrid(np.arange(n0, n1, dtype=np.float64),
+                             np.arange(m0, m1, dtype=np.float64), indexing="ij")
         dx, dy = xx - cx[e], yy - cy[e]
         u = (c * dx + s * dy) / ax[e]
         v = (-s * dx + c * dy) / ay[e]
         inside = (u * u + v * v) <= 1.0
-        img[inside] += amp[e] * complex(math.cos(ph[e]), math.sin(ph[e]))
+        img[n0:n1, m0:m1][inside] += amp[e] * complex(math.cos(ph[e]), math.sin(ph[e]))
     return img
 
 
