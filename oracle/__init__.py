@@ -31,7 +31,7 @@ uniqueness, an independent quasi-Newton minimiser).  Nothing is "parity
 unpinned".
 """
 from . import nudft, gram, toeplitz, penalty, criterion, solver  # noqa: F401
-from .nudft import forward, adjoint, dense_matrix  # noqa: F401
-from .gram import lag_kernel, paper_G, khat  # noqa: F401
+from .nudft import forward, adjoint, adjoint_at, dense_matrix  # noqa: F401
+from .gram import lag_kernel, lag_at, paper_G, khat, khat_at  # noqa: F401
 from .toeplitz import apply_gram, dense_gram  # noqa: F401
 from .solver import solve, solve_quadratic_dense  # noqa: F401

@@ -73,3 +73,15 @@ def dense_matrix(k: np.ndarray, N: int) -> np.ndarray:
     m = m.reshape(-1).astype(np.float64)
     ph = np.outer(k[:, 0], m) + np.outer(k[:, 1], n)
     return np.exp(2j * np.pi * ph) / N
+
+
+def adjoint_at(y: np.ndarray, k: np.ndarray, N: int, n, m) -> np.ndarray:
+    """Entries (A^H y)[n_i, m_i] by the direct sum of Eq. AnnMatGD.
+    y: [M]; n, m integer arrays.  For spot checks at large sizes."""
+    y = np.asarray(y, dtype=np.complex128)
+    n = np.asarray(n).ravel()
+    m = np.asarray(m).ravel()
+    out = np.empty(n.shape[0], dtype=np.complex128)
+    for i in range(n.shape[0]):
+        out[i] = np.sum(y * np.exp(-2j * np.pi * (k[:, 0] * m[i] + k[:, 1] * n[i])))
+    return out / N

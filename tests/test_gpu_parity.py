@@ -118,7 +118,10 @@ def test_gram_kernel_and_spectrum(N, L, karg):
 
 @pytest.mark.parametrize("N,L,karg,B", [(32, 64, (4, 256, 1.0), 1), (48, 128, (5, 199, 1.0), 2),
                                          (100, 256, (8, 313, 2.0), 3), (60, 256, (3, 500, 1.0), 1),
-                                         (256, 512, (16, 2048, 2.0), 2)])
+                                         (256, 512, (16, 2048, 2.0), 2),
+                                         (300, 1024, (12, 1500, 2.0), 2),
+                                         (40, 1024, (4, 300, 1.0), 1),
+                                         (40, 2048, (4, 300, 1.0), 2)])
 def test_gram_apply(N, L, karg, B):
     """Section 3.4: crop(IFFT(khat * FFT(pad v))) = A^H A v."""
     rng = np.random.default_rng(N + L)
@@ -198,6 +201,31 @@ def test_end_to_end_tiny_workload():
     assert e < 1e-4
     assert abs(st["J"][0] - h["J"][-1]) < 1e-5 * abs(h["J"][-1])
     assert st["status"][0] == 0 and st["iters_done"][0] == p.iters
+
+
+@pytest.mark.parametrize("N,L", [(40, 1024), (40, 2048), (300, 1024)])
+def test_end_to_end_long_transforms(N, L):
+    """The multi-wavefront FFT teams (L >= 1024, block barriers) through the
+    whole iteration: direction + row pass, column pass, inverse rows, update."""
+    # Fully sampled spirals (M ~ 0.5 N^2): in FP64 emulation a 3e-7 relative
+    # perturbation of b moves the 40-iteration result by ~2e-5 here, while a
+    # 0.08 N^2-sample spiral amplifies it ~2000-fold.
+    rng = np.random.default_rng(N + L)
+    k = spiral(N, 12, 4096, 1.0) if N > 100 else spiral(N, 4, 300, 2.0)
+    x_true = synthetic.ellipse_phantom(N, 8, rng)
+    y0 = oracle.forward(x_true, k)
+    y = (y0 + 0.01 * np.abs(y0).max() * synthetic.noise_draws(k.shape[0], rng))[None]
+    lam, delta, iters = 0.02, 0.05, 40
+    plan = recon.Plan(k, N, L, prec=recon.FP64)
+    plan.gram_kernel()
+    x, st = plan.solve(dev(y), lam, delta, iters)
+    b = oracle.adjoint(y[0].astype(np.complex64), k, N)
+    K = oracle.khat(k, N, L)
+    xo = oracle.solve(b, K, lam, delta, iters)
+    e = rel(host(x)[0], xo)
+    print(f"N={N} L={L} {iters} iterations: rel {e:.2e}")
+    assert e < 1e-4
+    assert st["status"][0] == 0
 
 
 def test_batch_invariance_and_determinism():

@@ -394,3 +394,41 @@ def test_planted_mistakes_are_caught(monkeypatch):
     fd = (criterion.J_direct(x + e, y, k, 0.5, 0.3)
           - criterion.J_direct(x - e, y, k, 0.5, 0.3)) / 2e-6
     assert abs(fd - gbad[1, 1].real) > 1e-4
+
+
+def test_spot_check_entries_agree_with_full_forms():
+    """The per-entry forms used for spot checks at large sizes agree with the
+    full forms: adjoint_at (direct sum) with the table/GEMM adjoint, lag_at
+    (direct sum) with lag_kernel, khat_at (closed-form geometric series per
+    sample) with the FFT of the circulant embedding, including frequencies
+    where a sample sits at an integer t (k = 0) and at the ends of the range."""
+    rng = np.random.default_rng(41)
+    N, L, M = 9, 19, 53
+    k = rand_k(rng, M)
+    k[0] = 0.0                      # t = p/L exactly at p = 0
+    k[1] = (-0.5, 0.5)              # range ends
+    y = rand_c(rng, M)
+    b = nudft.adjoint(y, k, N)
+    n = np.array([0, 8, 3, 8, 0])
+    m = np.array([0, 8, 5, 0, 7])
+    assert np.max(np.abs(nudft.adjoint_at(y, k, N, n, m) - b[n, m])) < 1e-13
+    h = gram.lag_kernel(k, N)
+    a = np.array([-(N - 1), 0, 3, N - 1, -2])
+    bb = np.array([N - 1, 0, -4, -(N - 1), 1])
+    assert np.max(np.abs(gram.lag_at(k, N, a, bb) - h[a + N - 1, bb + N - 1])) < 1e-15
+    K = gram.khat(k, N, L)
+    p = np.array([0, 0, 5, L - 1, 11, 18])
+    q = np.array([0, 7, 0, L - 1, 3, 9])
+    assert np.max(np.abs(gram.khat_at(k, N, L, p, q) - K[p, q])) < 1e-12 * np.abs(K).max()
+
+
+def test_spot_check_planted_mistake_is_caught():
+    """A sign error in the phase of the per-entry lag form is caught."""
+    rng = np.random.default_rng(42)
+    N, M = 6, 31
+    k = rand_k(rng, M)
+    h = gram.lag_kernel(k, N)
+    a, b = np.array([2]), np.array([-3])
+    wrong = np.sum(np.exp(+2j * np.pi * (k[:, 1] * a[0] + k[:, 0] * b[0]))) / N ** 2
+    assert abs(wrong - h[a[0] + N - 1, b[0] + N - 1]) > 1e-3
+    assert abs(gram.lag_at(k, N, a, b)[0] - h[a[0] + N - 1, b[0] + N - 1]) < 1e-15
