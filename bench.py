@@ -150,6 +150,9 @@ def main():
                     help="NUDFT contraction precision (fp64: FP64-accumulated adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=10)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB "
+                         "(reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -162,6 +165,15 @@ def main():
     recon.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration_mb:
+        nb = args.copy_calibration_mb << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes device to device")
+        del src, dst
     wl = WORKLOADS[args.workload]
     B = args.batch or wl["batch"]
     prob = synthetic.make_frames(wl["cfg"], frames=B)  # drifting phantoms, shared trajectory

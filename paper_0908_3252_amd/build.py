@@ -24,6 +24,9 @@ SOURCES = ["api.cpp", "nudft.hip", "nudft64.hip", "nudft_split.hip", "gram.hip",
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: avoids per-stage copies between
+    # the accumulation and architectural register files in the contractions
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(HERE, '..', 'include')}",
 ]

@@ -131,92 +131,157 @@ __global__ void k_split_reduce(size_t count, int splits, const float2* __restric
 }
 
 // ------------------------------------------------------------------ forward
-// grid: (l-tiles, B).  For each n-tile: P[n][l] = sum_m x[n][m] Ex[l][m]
-// (MFMA), then acc[l] += sum_n Ey[l][n] P[n][l]; y[l] = acc / N.
+// grid: (l-tiles, B).  For each 64-row n-tile: P[n][l] = sum_m x[n][m] Ex[l][m]
+// (MFMA, K = m in stages of FKT), then acc[l] += sum_n Ey[l][n] P[n][l];
+// y[l] = acc / N.
+//
+// Both operands are staged in LDS in their natural row-major form, one plane
+// per real component: X as [n][m] and Ex as [l][m] (row = MFMA row/column
+// index, contiguous = contraction index), row stride FLS = FKT + 4 floats so
+// that a fragment read (16 consecutive rows x 4 consecutive k) hits 64
+// distinct banks.  Global loads are coalesced (16 lanes per 32-element row)
+// and the next stage is prefetched into registers while the current one is
+// multiplied.  The epilogue's Ey tile reuses the staging memory.
+constexpr int FKT = 32;
+constexpr int FLS = FKT + 4;
+
+// Global -> registers: rows sr + 16 q (q < 4) of the x and Ex tiles, two
+// consecutive contraction indices from sc.  Out-of-range elements are loaded
+// from a clamped in-range address and zeroed only when stored (fwd_stash),
+// so nothing waits for the loads before the current stage's products.
+__device__ __forceinline__ void fwd_fetch(int64_t M, int N, const float2* __restrict__ xf,
+                                          const float2* __restrict__ ex, int64_t l0, int n0,
+                                          int m0, int sr, int sc, float2 (&px)[8],
+                                          float2 (&pe)[8]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = n0 + sr + 16 * q;
+    const int64_t l = l0 + sr + 16 * q;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int m = m0 + sc + v;
+      px[2 * q + v] = xf[(n < N && m < N) ? (size_t)n * N + m : 0];
+      pe[2 * q + v] = ex[(l < M && m < N) ? (size_t)l * N + m : 0];
+    }
+  }
+}
+
+// Registers -> LDS planes (row-major, stride FLS), zeroing out-of-range
+// elements of the stage (n0, m0).
+__device__ __forceinline__ void fwd_stash(int64_t M, int N, int64_t l0, int n0, int m0,
+                                          float* Xr, float* Xi, float* Er, float* Ei, int sr,
+                                          int sc, const float2 (&px)[8], const float2 (&pe)[8]) {
+  const float2 zero = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = n0 + sr + 16 * q;
+    const int64_t l = l0 + sr + 16 * q;
+    const bool m0ok = m0 + sc < N, m1ok = m0 + sc + 1 < N;
+    const float2 x0 = (n < N && m0ok) ? px[2 * q] : zero;
+    const float2 x1 = (n < N && m1ok) ? px[2 * q + 1] : zero;
+    const float2 e0 = (l < M && m0ok) ? pe[2 * q] : zero;
+    const float2 e1 = (l < M && m1ok) ? pe[2 * q + 1] : zero;
+    const int o = (sr + 16 * q) * FLS + sc;
+    *reinterpret_cast<float2*>(Xr + o) = make_float2(x0.x, x1.x);
+    *reinterpret_cast<float2*>(Xi + o) = make_float2(x0.y, x1.y);
+    *reinterpret_cast<float2*>(Er + o) = make_float2(e0.x, e1.x);
+    *reinterpret_cast<float2*>(Ei + o) = make_float2(e0.y, e1.y);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_forward_f32(int64_t M, int N,
                                                      const float2* __restrict__ ex,
                                                      const float2* __restrict__ ey,
                                                      const float2* __restrict__ x,
                                                      float2* __restrict__ y, float scale) {
-  __shared__ float Xr[KT][LDP], Xi[KT][LDP], Br[KT][LDP], Bi[KT][LDP];
-  __shared__ float2 Et[NT][NT + 1];  // Ey[l0 + j][n0 + i]
+  constexpr int PLANE = NT * FLS;            // floats per operand plane
+  constexpr int OPS = 4 * PLANE;             // Xr, Xi, Er, Ei
+  constexpr int EPS = NT * (NT + 1) * 2;     // Ey tile [64][65] complex, in floats
+  constexpr int SH = OPS > EPS ? OPS : EPS;
+  __shared__ __attribute__((aligned(16))) float sm[SH];
   __shared__ float2 red[4][2][16];
+  float* Xr = sm;
+  float* Xi = sm + PLANE;
+  float* Er = sm + 2 * PLANE;
+  float* Ei = sm + 3 * PLANE;
+  float2* Et = reinterpret_cast<float2*>(sm);
   const int f = blockIdx.y;
   const int64_t l0 = (int64_t)blockIdx.x * NT;
   const float2* xf = x + (size_t)f * N * N;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
-  float2 yacc[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-  const int lr = tid >> 4, lc = (tid & 15) * 4;  // loader: 16 k-rows x 64 columns
-
-  for (int n0 = 0; n0 < N; n0 += NT) {
-    v4f pr[2][2], pi[2][2];
+  // staging map: rows sr + 16 q (q < 4), two consecutive k from sc
+  const int sr = tid >> 4, sc = (tid & 15) * 2;
+  const float2 zero = make_float2(0.f, 0.f);
+  float2 px[8], pe[8];
+  float2 yacc[2] = {zero, zero};
+  v4f pr[2][2], pi[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) { pr[a][b] = v4f{0, 0, 0, 0}; pi[a][b] = v4f{0, 0, 0, 0}; }
-    for (int m0 = 0; m0 < N; m0 += KT) {
-      // A[i = n][k = m] = x[n0 + i][m0 + k];  B[k = m][j = l] = Ex[l0 + j][m0 + k]
-      const int m = m0 + lr;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int n = n0 + lc + c;
-        const int64_t l = l0 + lc + c;
-        const float2 xv = (n < N && m < N) ? xf[(size_t)n * N + m] : make_float2(0.f, 0.f);
-        const float2 ev = (l < M && m < N) ? ex[(size_t)l * N + m] : make_float2(0.f, 0.f);
-        Xr[lr][lc + c] = xv.x;
-        Xi[lr][lc + c] = xv.y;
-        Br[lr][lc + c] = ev.x;
-        Bi[lr][lc + c] = ev.y;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += 4) {
-        const int kr = kk + (lane >> 4), cc = lane & 15;
-        float ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          ar[a] = Xr[kr][wi + 16 * a + cc];
-          ai[a] = Xi[kr][wi + 16 * a + cc];
-        }
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          br[b] = Br[kr][wj + 16 * b + cc];
-          bi[b] = Bi[kr][wj + 16 * b + cc];
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            // x * Ex:  re = xr er - xi ei,  im = xr ei + xi er
-            pr[a][b] = mfma_f32_16x16x4(ar[a], br[b], pr[a][b]);
-            pr[a][b] = mfma_f32_16x16x4(-ai[a], bi[b], pr[a][b]);
-            pi[a][b] = mfma_f32_16x16x4(ar[a], bi[b], pi[a][b]);
-            pi[a][b] = mfma_f32_16x16x4(ai[a], br[b], pi[a][b]);
-          }
-      }
-      __syncthreads();
-    }
-    // Stage Ey[l0 + j][n0 + i] for the epilogue.
-    for (int idx = tid; idx < NT * NT; idx += 256) {
-      const int j = idx / NT, i = idx % NT;
-      const int64_t l = l0 + j;
-      const int n = n0 + i;
-      Et[j][i] = (l < M && n < N) ? ey[(size_t)l * N + n] : make_float2(0.f, 0.f);
-    }
+    for (int b = 0; b < 2; ++b) { pr[a][b] = v4f{0, 0, 0, 0}; pi[a][b] = v4f{0, 0, 0, 0}; }
+  const int nmt = (N + FKT - 1) / FKT;  // stages per n-tile
+  const int stages = ((N + NT - 1) / NT) * nmt;
+  fwd_fetch(M, N, xf, ex, l0, 0, 0, sr, sc, px, pe);
+  for (int st = 0; st < stages; ++st) {
+    const int n0 = (st / nmt) * NT;
+    fwd_stash(M, N, l0, n0, (st % nmt) * FKT, Xr, Xi, Er, Ei, sr, sc, px, pe);
     __syncthreads();
+    if (st + 1 < stages)
+      fwd_fetch(M, N, xf, ex, l0, ((st + 1) / nmt) * NT, ((st + 1) % nmt) * FKT, sr, sc, px, pe);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int j = wj + 16 * b + mfma16_col(lane);
+    for (int kk = 0; kk < FKT; kk += 4) {
+      const int kr = kk + (lane >> 4), cr = lane & 15;
+      float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = Xr[(wi + 16 * a + cr) * FLS + kr];
+        ai[a] = Xi[(wi + 16 * a + cr) * FLS + kr];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = Er[(wj + 16 * b + cr) * FLS + kr];
+        bi[b] = Ei[(wj + 16 * b + cr) * FLS + kr];
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = wi + 16 * a + mfma16_row(lane, r);
-          yacc[b] = c_add(yacc[b], c_mul(Et[j][i], make_float2(pr[a][b][r], pi[a][b][r])));
+        for (int b = 0; b < 2; ++b) {
+          // x * Ex:  re = xr er - xi ei,  im = xr ei + xi er
+          pr[a][b] = mfma_f32_16x16x4(ar[a], br[b], pr[a][b]);
+          pr[a][b] = mfma_f32_16x16x4(-ai[a], bi[b], pr[a][b]);
+          pi[a][b] = mfma_f32_16x16x4(ar[a], bi[b], pi[a][b]);
+          pi[a][b] = mfma_f32_16x16x4(ai[a], br[b], pi[a][b]);
         }
     }
-    __syncthreads();
+    if (st % nmt == nmt - 1) {
+      // Epilogue of the n-tile: acc[l] += sum_n Ey[l][n] P[n][l].
+      __syncthreads();  // staging reads done before Et overwrites them
+      for (int idx = tid; idx < NT * NT; idx += 256) {
+        const int j = idx / NT, i = idx % NT;
+        const int64_t l = l0 + j;
+        const int n = n0 + i;
+        Et[j * (NT + 1) + i] = (l < M && n < N) ? ey[(size_t)l * N + n] : zero;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = wj + 16 * b + mfma16_col(lane);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = wi + 16 * a + mfma16_row(lane, r);
+            yacc[b] = c_add(yacc[b], c_mul(Et[j * (NT + 1) + i],
+                                           make_float2(pr[a][b][r], pi[a][b][r])));
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) { pr[a][b] = v4f{0, 0, 0, 0}; pi[a][b] = v4f{0, 0, 0, 0}; }
+    }
+    __syncthreads();  // before the next stage overwrites the staging area
   }
   // Reduce over the row groups of a wave (lanes l, l^16, l^32, l^48) and
   // over the two waves sharing a column range.
@@ -236,7 +301,7 @@ __global__ __launch_bounds__(256) void k_forward_f32(int64_t M, int N,
   __syncthreads();
   if (tid < NT) {
     const int jb = tid / 32, rem = tid % 32, b = rem / 16, c = rem % 16;
-    // waves (0, 1) cover columns 0..31 (wj = 0 for w = 0, 2), wj = 32 for w = 1, 3
+    // waves 0 and 2 hold columns 0..31 (wj = 0), waves 1 and 3 columns 32..63
     const int wa = jb, wb = jb + 2;
     const float2 v = c_add(red[wa][b][c], red[wb][b][c]);
     const int64_t l = l0 + tid;
