@@ -85,8 +85,8 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
 }
 
 struct WsLayout {
-  size_t b, x[2], r, g, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, sc, adj, total;
-  int nb1, nb3, nb4, adj_splits;
+  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, sc, adj, total;
+  int rows, nb1, nb3, nb4, adj_splits;
 };
 
 WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
@@ -102,14 +102,14 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   w.x[0] = take(img);
   w.x[1] = take(img);
   w.r = take(img);
-  w.g = take(img);
   w.d[0] = take(img);
   w.d[1] = take(img);
   w.qd = take(img);
   w.T = take((size_t)B * N * L * sizeof(float2));
-  w.nb1 = cdiv(N, fft_rows_per_block(L));
+  w.rows = fft_rows_per_block(L);  // rows per block of every per-row kernel
+  w.nb1 = cdiv(N, w.rows);
   w.nb3 = L / fft_cols_per_block(L);  // <d, Qd> partials come from the column pass
-  w.nb4 = cdiv(N, upd_rows_per_block(N));
+  w.nb4 = cdiv(N, w.rows);
   w.p1 = take((size_t)B * w.nb1 * 2 * sizeof(double));
   w.p3 = take((size_t)B * w.nb3 * sizeof(double));
   w.p4 = take((size_t)B * w.nb4 * 4 * sizeof(double));
@@ -443,8 +443,8 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
     if (r != RECON_OK) return r;
     qx0 = w.img(w.lay.qd);
   }
-  HIP_TRY(launch_init(phi, N, B, b, reinterpret_cast<const float2*>(x0), qx0, w.img(w.lay.x[0]),
-                      w.img(w.lay.r), w.img(w.lay.g), w.img(w.lay.d[0]), w.dbl(w.lay.p4),
+  HIP_TRY(launch_init(phi, N, w.lay.rows, B, b, reinterpret_cast<const float2*>(x0), qx0,
+                      w.img(w.lay.x[0]), w.img(w.lay.r), w.img(w.lay.d[0]), w.dbl(w.lay.p4),
                       w.dbl(w.lay.pg0), w.params(), s));
   std::lock_guard<std::mutex> lk(p->mu);
   SolveCtx& c = p->solves[ws];
@@ -478,7 +478,7 @@ static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws
     float2* x_new = w.img(w.lay.x[(k + 1) & 1]);
     {
       TraceScope ts(TK_DIR, s);
-      HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, w.img(w.lay.g), d_old, d_new, x_old, T,
+      HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, w.img(w.lay.r), d_old, d_new, x_old, T,
                                 w.dbl(w.lay.p4), w.lay.nb4, w.dbl(w.lay.p1), w.params(), p->tw(),
                                 k, s));
     }
@@ -487,14 +487,10 @@ static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws
       HIP_TRY(launch_colpass(L, N, B, T, p->khat(), w.dbl(w.lay.p3), p->tw(), w.params(), k, s));
     }
     {
-      TraceScope ts(TK_ROWINV, s);
-      HIP_TRY(launch_rowifft(L, N, B, T, w.img(w.lay.qd), p->tw(), w.params(), k, s));
-    }
-    {
       TraceScope ts(TK_UPDATE, s);
-      HIP_TRY(launch_update(c.phi, N, B, x_old, x_new, d_new, w.img(w.lay.r), w.img(w.lay.qd),
-                            w.img(w.lay.g), w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3),
-                            w.lay.nb3, w.dbl(w.lay.p4), w.params(), k, s));
+      HIP_TRY(launch_update(L, c.phi, N, B, T, x_old, x_new, d_new, w.img(w.lay.r),
+                            w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3,
+                            w.dbl(w.lay.p4), w.params(), p->tw(), k, s));
     }
   }
   return RECON_OK;
@@ -537,10 +533,13 @@ recon_status_t recon_solve_export(recon_plan_t p, int32_t field, float* out, voi
   switch (field) {
     case 0: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.x[k & 1]), bytes, hipMemcpyDeviceToDevice, s)); break;
     case 1: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.r), bytes, hipMemcpyDeviceToDevice, s)); break;
-    case 2: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.g), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 2:
+      HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img(w.lay.x[k & 1]), w.img(w.lay.r),
+                            nullptr, w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, 0, s));
+      break;
     case 3:
-      HIP_TRY(launch_export_dir(p->N, c.B, w.img(w.lay.g), w.img(w.lay.d[k & 1]), o, w.dbl(w.lay.p4),
-                                w.lay.nb4, s));
+      HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img(w.lay.x[k & 1]), w.img(w.lay.r),
+                            w.img(w.lay.d[k & 1]), w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, 1, s));
       break;
     case 4: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.b), bytes, hipMemcpyDeviceToDevice, s)); break;
     default: return fail(RECON_E_ARG, "unknown field");
@@ -563,7 +562,8 @@ recon_status_t recon_solve_end(recon_plan_t p, float* x_out, recon_stats_t* stat
   const int k = c.iters;
   float2* x = w.img(w.lay.x[k & 1]);
   if (stats) {
-    HIP_TRY(launch_objective(c.phi, p->N, c.B, x, w.img(w.lay.b), w.img(w.lay.r), w.dbl(w.lay.pobj),
+    HIP_TRY(launch_objective(c.phi, p->N, w.lay.rows, c.B, x, w.img(w.lay.b), w.img(w.lay.r),
+                             w.dbl(w.lay.pobj),
                              w.params(), s));
     HIP_TRY(launch_stats(c.B, w.dbl(w.lay.pobj), w.lay.nb4, w.dbl(w.lay.p4), w.lay.nb4,
                          w.dbl(w.lay.pg0), w.lay.nb4, w.dbl(w.lay.yy), k, w.params(), stats, s));
@@ -647,9 +647,8 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, fl
   if (st != RECON_OK) return st;
   const int stop = k + iters;
   HIP_TRY(launch_set_params(1, lambda, delta, stop, w.params() + slot, s));
-  HIP_TRY(launch_init(c.phi, N, 1, w.img(w.lay.b) + fo, nullptr, nullptr,
-                      w.img(w.lay.x[k & 1]) + fo, w.img(w.lay.r) + fo, w.img(w.lay.g) + fo,
-                      w.img(w.lay.d[k & 1]) + fo, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
+  HIP_TRY(launch_init(c.phi, N, w.lay.rows, 1, w.img(w.lay.b) + fo, nullptr, nullptr,
+                      w.img(w.lay.x[k & 1]) + fo, w.img(w.lay.r) + fo, w.img(w.lay.d[k & 1]) + fo, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
                       w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.params() + slot, s));
   std::lock_guard<std::mutex> lk(p->mu);
   p->solves[ws].start_at[slot] = k;
@@ -695,7 +694,8 @@ recon_status_t recon_pool_retire(recon_plan_t p, int32_t slot, float* x_out, rec
   float2* x = w.img(w.lay.x[stop & 1]) + fo;
   if (stats) {
     double* pobj = w.dbl(w.lay.pobj) + (size_t)slot * w.lay.nb4 * 3;
-    HIP_TRY(launch_objective(c.phi, N, 1, x, w.img(w.lay.b) + fo, w.img(w.lay.r) + fo, pobj,
+    HIP_TRY(launch_objective(c.phi, N, w.lay.rows, 1, x, w.img(w.lay.b) + fo, w.img(w.lay.r) + fo,
+                             pobj,
                              w.params() + slot, s));
     HIP_TRY(launch_stats(1, pobj, w.lay.nb4, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
                          w.lay.nb4, w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.lay.nb4,

@@ -29,73 +29,11 @@ __global__ void k_set_params(int B, float lam, float delta, int stop_at, FramePa
   if (f < B) fp[f] = FrameParam{lam, delta, stop_at, 0};
 }
 
-// Rows n0-1 .. n0+ROWS of x (x_old + alpha d, or x as given) staged in LDS.
-template <int PHI>
-__global__ __launch_bounds__(256) void k_update(
-    int N, int ROWS, const float2* __restrict__ x_old, float2* __restrict__ x_new,
-    const float2* __restrict__ d, float2* __restrict__ r, const float2* __restrict__ qd,
-    float2* __restrict__ g, const double* __restrict__ p1, int nb1,
-    const double* __restrict__ p3, int nb3, double* __restrict__ p4,
-    const FrameParam* __restrict__ fp, int kit) {
-  extern __shared__ float2 xt[];  // [(ROWS+2)][N]
-  __shared__ double red[4 * 4];
-  const int f = blockIdx.y;
-  if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
-  const int n0 = blockIdx.x * ROWS;
-  const size_t fo = (size_t)f * N * N;
-  // Step length: exact minimiser of the half-quadratic majorant along d.
-  const double* q1 = p1 + (size_t)f * nb1 * 2;
-  const double gd = wave_sum_partials(q1 + 0, nb1, 2);
-  const double cv = wave_sum_partials(q1 + 1, nb1, 2);
-  const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
-  const FrameParam prm = fp[f];
-  const double den = 2.0 * dqd + (double)prm.lam * cv;
-  const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
-  const float af = (float)alpha;
-
-  const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);  // [r_lo, r_hi)
-  for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
-    const int rr = i / N, m = i - rr * N;
-    const size_t idx = fo + (size_t)(r_lo + rr) * N + m;
-    const float2 xv = x_old[idx], dv = d[idx];
-    xt[(r_lo + rr - (n0 - 1)) * N + m] = make_float2(fmaf(af, dv.x, xv.x), fmaf(af, dv.y, xv.y));
-  }
-  __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int own = min(ROWS, N - n0);
-  for (int i = threadIdx.x; i < own * N; i += 256) {
-    const int rr = i / N, m = i - rr * N;
-    const int n = n0 + rr;
-    const size_t idx = fo + (size_t)n * N + m;
-    const float2* mid = xt + (rr + 1) * N;
-    const float2* up = (n > 0) ? mid - N : nullptr;
-    const float2* dn = (n + 1 < N) ? mid + N : nullptr;
-    const float2 div = divergence<PHI>(up, mid, dn, m, N, prm.delta);
-    const float2 rv = r[idx], qv = qd[idx], go = g[idx], dv = d[idx];
-    const float2 rn = make_float2(fmaf(af, qv.x, rv.x), fmaf(af, qv.y, rv.y));
-    const float2 gn = make_float2(fmaf(prm.lam, div.x, 2.f * rn.x), fmaf(prm.lam, div.y, 2.f * rn.y));
-    x_new[idx] = mid[m];
-    r[idx] = rn;
-    g[idx] = gn;
-    const double gx = gn.x, gy = gn.y;
-    acc[0] += gx * gx + gy * gy;
-    acc[1] += gx * (double)go.x + gy * (double)go.y;
-    acc[2] += gx * (double)dv.x + gy * (double)dv.y;
-    acc[3] += (double)go.x * (double)go.x + (double)go.y * (double)go.y;
-  }
-  block_sum<4>(acc, red);
-  if (threadIdx.x == 0) {
-    double* o = p4 + ((size_t)f * gridDim.x + blockIdx.x) * 4;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = acc[k];
-  }
-}
-
 template <int PHI>
 __global__ __launch_bounds__(256) void k_init(
     int N, int ROWS, const float2* __restrict__ b, const float2* __restrict__ x0,
     const float2* __restrict__ qx0, float2* __restrict__ x, float2* __restrict__ r,
-    float2* __restrict__ g, float2* __restrict__ d, double* __restrict__ p4,
+    float2* __restrict__ d, double* __restrict__ p4,
     double* __restrict__ pg0, const FrameParam* __restrict__ fp) {
   extern __shared__ float2 xt[];
   __shared__ double red[1 * 4];
@@ -126,7 +64,6 @@ __global__ __launch_bounds__(256) void k_init(
     const float2 gn = make_float2(fmaf(prm.lam, div.x, 2.f * rn.x), fmaf(prm.lam, div.y, 2.f * rn.y));
     x[idx] = mid[m];
     r[idx] = rn;
-    g[idx] = gn;
     d[idx] = make_float2(0.f, 0.f);
     acc[0] += (double)gn.x * (double)gn.x + (double)gn.y * (double)gn.y;
   }
@@ -215,23 +152,55 @@ __global__ void k_stats(int B, const double* __restrict__ pobj, int nbo,
   }
 }
 
-__global__ void k_export_dir(int N, const float2* __restrict__ g, const float2* __restrict__ d_old,
-                             float2* __restrict__ out, const double* __restrict__ p4, int nb4) {
+// The gradient g = 2 r + lam D^T(w(Dx) Dx) of the current iterate, or the
+// pending direction -g + beta d_old (as the next direction kernel forms
+// it), into out.  Rows n0-1 .. n0+ROWS of x are staged in LDS.
+template <int PHI>
+__global__ __launch_bounds__(256) void k_export(int N, int ROWS, const float2* __restrict__ x,
+                                                const float2* __restrict__ r,
+                                                const float2* __restrict__ d_old,
+                                                const double* __restrict__ p4, int nb4,
+                                                const FrameParam* __restrict__ fp,
+                                                float2* __restrict__ out, int dir) {
+  extern __shared__ float2 xt[];
   const int f = blockIdx.y;
-  const double* pf = p4 + (size_t)f * nb4 * 4;
-  const double gg = wave_sum_partials(pf + 0, nb4, 4);
-  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
-  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
-  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
-  double beta = 0.0;
-  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
-  if (-gg + beta * gdo >= 0.0) beta = 0.0;
-  const float bf = (float)beta;
+  const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)N * N;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const float2 gv = g[fo + i], dv = d_old[fo + i];
-    out[fo + i] = make_float2(fmaf(bf, dv.x, -gv.x), fmaf(bf, dv.y, -gv.y));
+  const FrameParam prm = fp[f];
+  float bf = 0.f;
+  if (dir) {
+    const double* pf = p4 + (size_t)f * nb4 * 4;
+    const double gg = wave_sum_partials(pf + 0, nb4, 4);
+    const double ggo = wave_sum_partials(pf + 1, nb4, 4);
+    const double gdo = wave_sum_partials(pf + 2, nb4, 4);
+    const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+    double beta = 0.0;
+    if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
+    if (-gg + beta * gdo >= 0.0) beta = 0.0;
+    bf = (float)beta;
+  }
+  const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);
+  for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    xt[(r_lo + rr - (n0 - 1)) * N + m] = x[fo + (size_t)(r_lo + rr) * N + m];
+  }
+  __syncthreads();
+  const int own = min(ROWS, N - n0);
+  for (int i = threadIdx.x; i < own * N; i += 256) {
+    const int rr = i / N, m = i - rr * N;
+    const int n = n0 + rr;
+    const size_t idx = fo + (size_t)n * N + m;
+    const float2* mid = xt + (rr + 1) * N;
+    const float2 div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                       n + 1 < N ? mid + N : nullptr, m, N, prm.delta);
+    const float2 rv = r[idx];
+    const float2 g = make_float2(fmaf(prm.lam, div.x, 2.f * rv.x), fmaf(prm.lam, div.y, 2.f * rv.y));
+    if (dir) {
+      const float2 dv = d_old[idx];
+      out[idx] = make_float2(fmaf(bf, dv.x, -g.x), fmaf(bf, dv.y, -g.y));
+    } else {
+      out[idx] = g;
+    }
   }
 }
 
@@ -255,33 +224,19 @@ hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FramePa
   return hipGetLastError();
 }
 
-hipError_t launch_update(int phi, int N, int B, const float2* x_old, float2* x_new,
-                         const float2* d, float2* r, const float2* qd, float2* g,
-                         const double* p1, int nb1, const double* p3, int nb3,
-                         double* p4, const FrameParam* fp, int k, hipStream_t s) {
-  const int R = upd_rows_per_block(N);
-  dim3 grid(cdiv(N, R), B);
-  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
-  RECON_PHI_SWITCH(phi, (k_update<PP><<<grid, 256, shm, s>>>(N, R, x_old, x_new, d, r, qd, g,
-                                                             p1, nb1, p3, nb3, p4, fp, k)));
-  return hipGetLastError();
-}
-
-hipError_t launch_init(int phi, int N, int B, const float2* b, const float2* x0,
-                       const float2* qx0, float2* x, float2* r, float2* g, float2* d,
+hipError_t launch_init(int phi, int N, int R, int B, const float2* b, const float2* x0,
+                       const float2* qx0, float2* x, float2* r, float2* d,
                        double* p4, double* pg0, const FrameParam* fp, hipStream_t s) {
-  const int R = upd_rows_per_block(N);
   dim3 grid(cdiv(N, R), B);
   const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
-  RECON_PHI_SWITCH(phi, (k_init<PP><<<grid, 256, shm, s>>>(N, R, b, x0, qx0, x, r, g, d, p4,
+  RECON_PHI_SWITCH(phi, (k_init<PP><<<grid, 256, shm, s>>>(N, R, b, x0, qx0, x, r, d, p4,
                                                            pg0, fp)));
   return hipGetLastError();
 }
 
-hipError_t launch_objective(int phi, int N, int B, const float2* x, const float2* b,
+hipError_t launch_objective(int phi, int N, int R, int B, const float2* x, const float2* b,
                             const float2* r, double* pobj, const FrameParam* fp,
                             hipStream_t s) {
-  const int R = upd_rows_per_block(N);
   dim3 grid(cdiv(N, R), B);
   RECON_PHI_SWITCH(phi, (k_objective<PP><<<grid, 256, 0, s>>>(N, R, x, b, r, pobj, fp)));
   return hipGetLastError();
@@ -295,10 +250,13 @@ hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4, in
   return hipGetLastError();
 }
 
-hipError_t launch_export_dir(int N, int B, const float2* g, const float2* d_old, float2* out,
-                             const double* p4, int nb4, hipStream_t s) {
-  dim3 grid(cdiv(N * N, 256 * 4), B);
-  k_export_dir<<<grid, 256, 0, s>>>(N, g, d_old, out, p4, nb4);
+hipError_t launch_export(int phi, int N, int R, int B, const float2* x, const float2* r,
+                         const float2* d_old, const double* p4, int nb4, const FrameParam* fp,
+                         float2* out, int dir, hipStream_t s) {
+  dim3 grid(cdiv(N, R), B);
+  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
+  RECON_PHI_SWITCH(phi, (k_export<PP><<<grid, 256, shm, s>>>(N, R, x, r, d_old, p4, nb4, fp, out,
+                                                             dir)));
   return hipGetLastError();
 }
 

@@ -1,0 +1,372 @@
+// One iteration of the pseudo-conjugate gradient (Section 3.3) around the
+// Toeplitz Gram apply (Section 3.4), as two row kernels on either side of
+// the column pass:
+//
+//   k_dir_rowfft   g = 2 r + lam D^T(w(Dx) Dx)          (recomputed, not stored)
+//                  d = -g + beta d_old                   (PR+ with restart)
+//                  partials Re<g, d>, sum w(|Dx|) |Dd|^2 (step length)
+//                  T[n][:] = FFT_L(pad d[n][:])          (row pass)
+//   k_colpass      column FFT, x khat, column IFFT, <d, Qd> partials
+//   k_update       Qd[n][:] = IFFT_L(T[n][:]) cropped    (row inverse pass)
+//                  alpha = -Re<g, d> / (2 Re<d, Qd> + lam sum w |Dd|^2)
+//                  x += alpha d, r += alpha Qd, g_new = 2 r + lam grad R(x),
+//                  partials |g_new|^2, Re<g_new, g>, Re<g_new, d>, |g|^2
+//
+// A block owns ROWS = 2048 / L image rows, one FFT team (L/8 threads) per
+// row; thread t of the team owns the pixels m = t + e L/8 (e < 4) of its row,
+// which is exactly the layout the FFT team takes in and gives out, so pixel
+// data, the transform and the update stay in registers.  Every global load
+// of a thread (own pixels and its share of the one- or two-row halos that
+// the stencil needs) is issued before the first use.  The gradient is
+// rebuilt from r and x wherever it is needed with the same operations in the
+// same order, so every copy of it is bitwise the same.
+#include "fft.hpp"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace recon {
+
+template <int L>
+struct RowCfg {
+  static constexpr int TT = L / 8;        // threads per row team
+  static constexpr int ROWS = 256 / TT;   // rows per block
+  static constexpr int W = L / 2;         // widest image row (N <= L/2)
+  static constexpr int EPT = W / TT;      // own pixels per thread (4)
+};
+
+// g = 2 r + lam * div, as every kernel forms it.
+__device__ __forceinline__ float2 grad_from(float2 r, float2 div, float lam) {
+  return make_float2(fmaf(lam, div.x, 2.f * r.x), fmaf(lam, div.y, 2.f * r.y));
+}
+
+// ------------------------------------------------------- direction + rows
+template <int L, int PHI>
+__global__ __launch_bounds__(256) void k_dir_rowfft(
+    int N, const float2* __restrict__ r, const float2* __restrict__ d_old,
+    float2* __restrict__ d_new, const float2* __restrict__ x, float2* __restrict__ T,
+    const double* __restrict__ p4, int nb4, double* __restrict__ p1,
+    const FrameParam* __restrict__ fp, const float2* __restrict__ twg, int kit) {
+  using C = RowCfg<L>;
+  constexpr int TT = C::TT, ROWS = C::ROWS, W = C::W, EPT = C::EPT;
+  constexpr int XT = (ROWS + 3) * W;      // x rows n0-1 .. n0+ROWS+1
+  constexpr int DT = (ROWS + 1) * W;      // d rows n0 .. n0+ROWS
+  constexpr int FFTB = ROWS * fft_team_lds<L>();
+  constexpr int SH = (XT + DT > FFTB) ? XT + DT : FFTB;
+  constexpr int HX = (3 * W + 255) / 256;  // x halo elements per thread (3 rows)
+  constexpr int HD = (W + 255) / 256;      // r, d halo elements per thread (1 row)
+  if (kit >= fp[blockIdx.y].stop_at) return;  // frame idle in this iteration (block-uniform)
+  __shared__ float2 tw[L];
+  __shared__ float2 sh[SH];
+  __shared__ double red[2 * 4];
+  float2* Xt = sh;       // tile row i <-> image row n0 - 1 + i (stride N)
+  float2* Dt = sh + XT;  // tile row i <-> image row n0 + i
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  const int team = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int n = n0 + team;
+  const float2 zero = make_float2(0.f, 0.f);
+
+  // -- loads: own pixels, then the halo rows
+  float2 xo[EPT], ro[EPT], dv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    const size_t idx = (n < N && m < N) ? fo + (size_t)n * N + m : 0;
+    xo[e] = x[idx];
+    ro[e] = r[idx];
+    dv[e] = d_old[idx];
+  }
+  float2 hx[HX], hr[HD], hd[HD];
+#pragma unroll
+  for (int s = 0; s < HX; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / N, m = j - sel * N;  // sel 0: n0-1, 1: n0+ROWS, 2: n0+ROWS+1
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS + sel - 1;
+    const bool ok = j < 3 * N && img >= 0 && img < N;
+    hx[s] = x[ok ? fo + (size_t)img * N + m : 0];
+  }
+#pragma unroll
+  for (int s = 0; s < HD; ++s) {
+    const int m = threadIdx.x + s * 256;
+    const bool ok = m < N && n0 + ROWS < N;
+    const size_t idx = ok ? fo + (size_t)(n0 + ROWS) * N + m : 0;
+    hr[s] = r[idx];
+    hd[s] = d_old[idx];
+  }
+  load_twiddles<L>(tw, twg);
+
+  // beta of the Polak-Ribiere (PR+) correction, with restart, from the
+  // update kernel's partials [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
+  const double* pf = p4 + (size_t)f * nb4 * 4;
+  const double gg = wave_sum_partials(pf + 0, nb4, 4);
+  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
+  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
+  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+  double beta = 0.0;
+  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
+  if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
+  const float bf = (float)beta;
+  const float lam = fp[f].lam, delta = fp[f].delta;
+
+  // -- x tile
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) Xt[(team + 1) * N + m] = xo[e];
+  }
+#pragma unroll
+  for (int s = 0; s < HX; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / N, m = j - sel * N;
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS + sel - 1;
+    if (j < 3 * N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
+  }
+  __syncthreads();
+
+  // -- gradient and new direction: own rows and the halo row n0 + ROWS
+  double gd = 0.0;
+  float2 dn[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    dn[e] = zero;
+    if (n < N && m < N) {
+      const float2* mid = Xt + (team + 1) * N;
+      const float2 div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                         n + 1 < N ? mid + N : nullptr, m, N, delta);
+      const float2 g = grad_from(ro[e], div, lam);
+      dn[e] = make_float2(fmaf(bf, dv[e].x, -g.x), fmaf(bf, dv[e].y, -g.y));
+      Dt[team * N + m] = dn[e];
+      d_new[fo + (size_t)n * N + m] = dn[e];
+      gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
+    }
+  }
+  if (n0 + ROWS < N) {
+    const int nh = n0 + ROWS;
+#pragma unroll
+    for (int s = 0; s < HD; ++s) {
+      const int m = threadIdx.x + s * 256;
+      if (m < N) {
+        const float2* mid = Xt + (ROWS + 1) * N;
+        const float2 div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N,
+                                           delta);
+        const float2 g = grad_from(hr[s], div, lam);
+        Dt[ROWS * N + m] = make_float2(fmaf(bf, hd[s].x, -g.x), fmaf(bf, hd[s].y, -g.y));
+      }
+    }
+  }
+  __syncthreads();
+
+  // -- curvature of the half-quadratic majorant along d (own rows)
+  double cv = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) {
+      const float2 x0 = Xt[(team + 1) * N + m], e0 = Dt[team * N + m];
+      if (n + 1 < N) {
+        const float2 tx = c_sub(Xt[(team + 2) * N + m], x0);
+        const float2 te = c_sub(Dt[(team + 1) * N + m], e0);
+        cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+      }
+      if (m + 1 < N) {
+        const float2 tx = c_sub(Xt[(team + 1) * N + m + 1], x0);
+        const float2 te = c_sub(Dt[team * N + m + 1], e0);
+        cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+      }
+    }
+  }
+  double v2[2] = {gd, cv};
+  block_sum<2>(v2, red);  // ends with a block barrier: the tiles are free
+  if (threadIdx.x == 0) {
+    double* o = p1 + ((size_t)f * gridDim.x + blockIdx.x) * 2;
+    o[0] = v2[0];
+    o[1] = v2[1];
+  }
+
+  // -- row FFT of d (team layout in = own pixels)
+  float2 val[8];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) val[e] = dn[e];
+  fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L>(),
+                           sh + team * fft_team_lds<L>() +
+                               (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD),
+                           tw);
+  if (n < N) {
+    float2* out = T + ((size_t)f * N + n) * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[t + e * TT] = val[e];
+  }
+}
+
+// ------------------------------------------------ inverse rows + update
+template <int L, int PHI>
+__global__ __launch_bounds__(256) void k_update(
+    int N, const float2* __restrict__ T, const float2* __restrict__ x_old,
+    float2* __restrict__ x_new, const float2* __restrict__ d, float2* __restrict__ r,
+    const double* __restrict__ p1, int nb1, const double* __restrict__ p3, int nb3,
+    double* __restrict__ p4, const FrameParam* __restrict__ fp, const float2* __restrict__ twg,
+    int kit) {
+  using C = RowCfg<L>;
+  constexpr int TT = C::TT, ROWS = C::ROWS, W = C::W, EPT = C::EPT;
+  constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
+  constexpr int FFTB = ROWS * fft_team_lds<L>();
+  constexpr int SH = (2 * XT > FFTB) ? 2 * XT : FFTB;
+  constexpr int HX = (2 * W + 255) / 256;  // halo elements per thread (2 rows)
+  if (kit >= fp[blockIdx.y].stop_at) return;
+  __shared__ float2 tw[L];
+  __shared__ float2 sh[SH];
+  __shared__ double red[4 * 4];
+  float2* Xo = sh;       // x at the start of the iteration; row i <-> image row n0-1+i
+  float2* Xn = sh + XT;  // x + alpha d
+  const int f = blockIdx.y;
+  const int n0 = blockIdx.x * ROWS;
+  const size_t fo = (size_t)f * N * N;
+  const int team = threadIdx.x / TT, t = threadIdx.x % TT;
+  const int n = n0 + team;
+
+  // -- loads: the transformed row, own pixels, halo rows
+  float2 val[8];
+  {
+    const float2* row = T + ((size_t)f * N + (n < N ? n : 0)) * L;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) val[e] = row[t + e * TT];
+  }
+  float2 xo[EPT], dv[EPT], ro[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    const size_t idx = (n < N && m < N) ? fo + (size_t)n * N + m : 0;
+    xo[e] = x_old[idx];
+    dv[e] = d[idx];
+    ro[e] = r[idx];
+  }
+  float2 hx[HX], hd[HX];
+#pragma unroll
+  for (int s = 0; s < HX; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / N, m = j - sel * N;  // sel 0: n0-1, 1: n0+ROWS
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+    const bool ok = j < 2 * N && img >= 0 && img < N;
+    const size_t idx = ok ? fo + (size_t)img * N + m : 0;
+    hx[s] = x_old[idx];
+    hd[s] = d[idx];
+  }
+  load_twiddles<L>(tw, twg);
+
+  // Step length: exact minimiser of the half-quadratic majorant along d.
+  const double* q1 = p1 + (size_t)f * nb1 * 2;
+  const double gd = wave_sum_partials(q1 + 0, nb1, 2);
+  const double cvv = wave_sum_partials(q1 + 1, nb1, 2);
+  const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
+  const float lam = fp[f].lam, delta = fp[f].delta;
+  const double den = 2.0 * dqd + (double)lam * cvv;
+  const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
+  const float af = (float)alpha;
+  __syncthreads();  // twiddles
+
+  // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
+  fft_team<L, true, false>(val, t, sh + team * fft_team_lds<L>(),
+                           sh + team * fft_team_lds<L>() +
+                               (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD),
+                           tw);
+  __syncthreads();  // FFT buffers become the x tiles
+
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) {
+      Xo[(team + 1) * N + m] = xo[e];
+      Xn[(team + 1) * N + m] = make_float2(fmaf(af, dv[e].x, xo[e].x), fmaf(af, dv[e].y, xo[e].y));
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < HX; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / N, m = j - sel * N;
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+    if (j < 2 * N && img >= 0 && img < N) {
+      const int o = (img - n0 + 1) * N + m;
+      Xo[o] = hx[s];
+      Xn[o] = make_float2(fmaf(af, hd[s].x, hx[s].x), fmaf(af, hd[s].y, hx[s].y));
+    }
+  }
+  __syncthreads();
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) {
+      const size_t idx = fo + (size_t)n * N + m;
+      const float2* mo = Xo + (team + 1) * N;
+      const float2* mn = Xn + (team + 1) * N;
+      const float2 div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
+                                           n + 1 < N ? mo + N : nullptr, m, N, delta);
+      const float2 div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
+                                           n + 1 < N ? mn + N : nullptr, m, N, delta);
+      const float2 go = grad_from(ro[e], div_o, lam);
+      const float2 rn = make_float2(fmaf(af, val[e].x, ro[e].x), fmaf(af, val[e].y, ro[e].y));
+      const float2 gn = grad_from(rn, div_n, lam);
+      x_new[idx] = mn[m];
+      r[idx] = rn;
+      const double gx = gn.x, gy = gn.y;
+      acc[0] += gx * gx + gy * gy;
+      acc[1] += gx * (double)go.x + gy * (double)go.y;
+      acc[2] += gx * (double)dv[e].x + gy * (double)dv[e].y;
+      acc[3] += (double)go.x * (double)go.x + (double)go.y * (double)go.y;
+    }
+  }
+  block_sum<4>(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = p4 + ((size_t)f * gridDim.x + blockIdx.x) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = acc[k];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+#define RECON_ITER_L_SWITCH(L_, CALL)                    \
+  switch (L_) {                                          \
+    case 64: { constexpr int LL = 64; CALL; } break;     \
+    case 128: { constexpr int LL = 128; CALL; } break;   \
+    case 256: { constexpr int LL = 256; CALL; } break;   \
+    case 512: { constexpr int LL = 512; CALL; } break;   \
+    case 1024: { constexpr int LL = 1024; CALL; } break; \
+    case 2048: { constexpr int LL = 2048; CALL; } break; \
+    default: return hipErrorInvalidValue;                \
+  }
+#define RECON_ITER_PHI_SWITCH(PHI_, CALL)             \
+  switch (PHI_) {                                     \
+    case 0: { constexpr int PP = 0; CALL; } break;    \
+    case 1: { constexpr int PP = 1; CALL; } break;    \
+    case 2: { constexpr int PP = 2; CALL; } break;    \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
+                             const float2* d_old, float2* d_new, const float2* x, float2* T,
+                             const double* p4, int nb4, double* p1, const FrameParam* fp,
+                             const float2* tw, int k, hipStream_t s) {
+  if (N > L / 2) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP><<<grid, 256, 0, s>>>(
+                                                        N, r, d_old, d_new, x, T, p4, nb4, p1,
+                                                        fp, tw, k))));
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
+                         float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
+                         const double* p3, int nb3, double* p4, const FrameParam* fp,
+                         const float2* tw, int k, hipStream_t s) {
+  if (N > L / 2) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP><<<grid, 256, 0, s>>>(
+                                                        N, T, x_old, x_new, d, r, p1, nb1, p3,
+                                                        nb3, p4, fp, tw, k))));
+  return hipGetLastError();
+}
+
+}  // namespace recon

@@ -24,8 +24,6 @@ struct FrameParam {
 inline int fft_rows_per_block(int L) { return 2048 / L; }
 // Columns handled by one block of the column kernel.
 int fft_cols_per_block(int L);
-// Rows per block of the elementwise update kernel.
-inline int upd_rows_per_block(int N) { return N > 512 ? 4 : 8; }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -45,54 +43,52 @@ hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
 
 
 // ---- CG kernels (Section 3.3) -------------------------------------------------
-// Direction update d_new = -g + beta d_old (beta from the update partials,
-// PR+ with restart), partials Re<g, d_new> and sum w(x)|D d_new|^2, and the
-// row pass of the Gram apply on d_new.
-hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
-                             const float2* d_old, float2* d_new,
-                             const float2* x, float2* T, const double* p4,
-                             int nb4, double* p1, const FrameParam* fp,
+// Rows per block of the iteration kernels (one FFT team of L/8 threads per row).
+// The step-length partials p1 and the update partials p4 have cdiv(N, rows)
+// entries per frame.
+// Direction: g = 2 r + grad R(x) (recomputed), d_new = -g + beta d_old (beta
+// from the update partials, PR+ with restart), partials Re<g, d_new> and
+// sum w(x)|D d_new|^2, and the row pass of the Gram apply on d_new.
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
+                             const float2* d_old, float2* d_new, const float2* x, float2* T,
+                             const double* p4, int nb4, double* p1, const FrameParam* fp,
                              const float2* tw, int k, hipStream_t s);
-// alpha from the partials; x_new = x + alpha d, r += alpha Qd,
-// g = 2 r + lam D^T(w(D x_new) D x_new); partials for beta.
-hipError_t launch_update(int phi, int N, int B, const float2* x_old,
-                         float2* x_new, const float2* d, float2* r,
-                         const float2* qd, float2* g, const double* p1,
-                         int nb1, const double* p3, int nb3, double* p4,
-                         const FrameParam* fp, int k, hipStream_t s);
-// Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), g = 2r +
-// grad R(x0), d = 0; partials such that the first direction is -g.
-hipError_t launch_init(int phi, int N, int B, const float2* b,
+// Row inverse pass of the Gram apply fused with the update: Qd = rows of
+// IFFT(T) cropped; alpha from the partials; x_new = x + alpha d,
+// r += alpha Qd; partials for beta from g_old (recomputed from r, x) and
+// g_new = 2 r + grad R(x_new).
+hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
+                         float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
+                         const double* p3, int nb3, double* p4, const FrameParam* fp,
+                         const float2* tw, int k, hipStream_t s);
+// Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), d = 0; partials
+// such that the first direction is -g, g = 2r + grad R(x0).  R rows per block.
+hipError_t launch_init(int phi, int N, int R, int B, const float2* b,
                        const float2* x0, const float2* qx0, float2* x,
-                       float2* r, float2* g, float2* d, double* p4,
+                       float2* r, float2* d, double* p4,
                        double* pg0, const FrameParam* fp, hipStream_t s);
 hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s);
 hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp,
                              hipStream_t s);
 // Objective partials and final statistics.
-hipError_t launch_objective(int phi, int N, int B, const float2* x,
+hipError_t launch_objective(int phi, int N, int R, int B, const float2* x,
                             const float2* b, const float2* r, double* pobj,
                             const FrameParam* fp, hipStream_t s);
 hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4,
                         int nb4, const double* pg0, int nbg, const double* yy,
                         int iters, const FrameParam* fp, void* stats,
                         hipStream_t s);
-// Materialise the pending direction -g + beta d_old (as the next direction
-// kernel would) into out.
-hipError_t launch_export_dir(int N, int B, const float2* g, const float2* d_old,
-                             float2* out, const double* p4, int nb4,
-                             hipStream_t s);
+// The gradient (dir = 0) or the pending direction -g + beta d_old (dir = 1,
+// as the next direction kernel would form it) of the current iterate.
+hipError_t launch_export(int phi, int N, int R, int B, const float2* x, const float2* r,
+                         const float2* d_old, const double* p4, int nb4, const FrameParam* fp,
+                         float2* out, int dir, hipStream_t s);
 
 // ---- NUDFT (Section 2, Appendix A.2) -------------------------------------------
 // Phasor tables E[l][j] = exp(i 2 pi k_l j), j < N, FP32 complex, for both
 // axes: ex from k_x, ey from k_y.  k: device float64 [M][2].
 hipError_t launch_tables_f32(int64_t M, int N, const double* k, float2* ex,
                              float2* ey, hipStream_t s);
-// Split-precision tables: hi = round(E), lo = round(E - hi) in bf16 (prec 1)
-// or fp16 (prec 2), planes [M][N] of (re, im) pairs.
-hipError_t launch_tables_split(int prec, int64_t M, int N, const float2* ex,
-                               const float2* ey, void* ex_hi, void* ex_lo,
-                               void* ey_hi, void* ey_lo, hipStream_t s);
 // Adjoint: b[f][n][m] = (1/N) sum_l conj(ey[l][n]) y[f][l] conj(ex[l][m]).
 // Split-K over `splits` sample ranges into part[s][f][n][m] when splits > 1.
 int adjoint_splits(int64_t M, int N);

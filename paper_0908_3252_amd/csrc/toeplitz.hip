@@ -11,9 +11,9 @@
 //   column pass   T[N][L]  -> T[N][L]      (column FFT, x khat, column IFFT,
 //                                           in place, tiles staged in LDS)
 //   row inverse   T[N][L]  -> Qv[N][N]     (row IFFTs, first N outputs kept)
-// The direction update of the conjugate gradient (and its step-length
-// partials) is fused into the row pass; the <d, Qd> partial is taken in the
-// column pass (Parseval).
+// Inside the iteration the row passes are fused with the conjugate-gradient
+// direction and update kernels (iterate.hip); the <d, Qd> partial is taken
+// in the column pass (Parseval).
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -59,105 +59,6 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __res
   }
 }
 
-// --------------------------------------------- CG direction + row pass (fused)
-// Block = ROWS image rows of frame f.  Phase A builds d_new = -g + beta d_old
-// for the block's rows plus one halo row below (recomputed bit-identically
-// by the owner block) in LDS, together with x; phase B forms the partials
-// Re<g, d_new> and sum w(|D x|) |D d_new|^2; phase C transforms the rows.
-template <int L, int PHI>
-__global__ __launch_bounds__(256) void k_dir_rowfft(
-    int N, const float2* __restrict__ g, const float2* __restrict__ d_old,
-    float2* __restrict__ d_new, const float2* __restrict__ x, float2* __restrict__ T,
-    const double* __restrict__ p4, int nb4, double* __restrict__ p1,
-    const FrameParam* __restrict__ fp, const float2* __restrict__ twg, int kit) {
-  using S = FftShape<L>;
-  constexpr int ROWS = 256 / S::T;
-  constexpr int TILE = (ROWS + 1) * (L / 2);
-  if (kit >= fp[blockIdx.y].stop_at) return;  // frame idle in this iteration (block-uniform)
-  constexpr int FFTB = ROWS * fft_team_lds<L>();
-  constexpr int SH = (2 * TILE > FFTB) ? 2 * TILE : FFTB;
-  __shared__ float2 tw[L];
-  __shared__ float2 sh[SH];
-  __shared__ double red[2 * 4];
-  float2* Dt = sh;          // [ROWS+1][N] d_new (phase A/B), aliased by FFT buffers
-  float2* Xt = sh + TILE;   // [ROWS+1][N] x
-  const int f = blockIdx.y;
-  const int n0 = blockIdx.x * ROWS;
-  const size_t fo = (size_t)f * N * N;
-  load_twiddles<L>(tw, twg);
-
-  // beta of the Polak-Ribiere (PR+) correction, with restart, from the
-  // update kernel's partials: [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
-  const double* pf = p4 + (size_t)f * nb4 * 4;
-  const double gg = wave_sum_partials(pf + 0, nb4, 4);
-  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
-  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
-  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
-  double beta = 0.0;
-  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
-  if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
-  const float bf = (float)beta;
-
-  // Phase A
-  const int nrows = min(ROWS + 1, N - n0);
-  double gd = 0.0;
-  for (int i = threadIdx.x; i < nrows * N; i += 256) {
-    const int rr = i / N, m = i - rr * N;
-    const size_t idx = fo + (size_t)(n0 + rr) * N + m;
-    const float2 gv = g[idx], dv = d_old[idx];
-    const float2 dn = make_float2(fmaf(bf, dv.x, -gv.x), fmaf(bf, dv.y, -gv.y));
-    Dt[rr * N + m] = dn;
-    Xt[rr * N + m] = x[idx];
-    if (rr < ROWS) {
-      d_new[idx] = dn;
-      gd += (double)gv.x * (double)dn.x + (double)gv.y * (double)dn.y;
-    }
-  }
-  __syncthreads();
-  // Phase B: curvature of the half-quadratic majorant along d_new.
-  const float delta = fp[f].delta;
-  double cv = 0.0;
-  const int own = min(ROWS, N - n0);
-  for (int i = threadIdx.x; i < own * N; i += 256) {
-    const int rr = i / N, m = i - rr * N;
-    const int n = n0 + rr;
-    const float2 x0 = Xt[rr * N + m], e0 = Dt[rr * N + m];
-    if (n + 1 < N) {
-      const float2 tx = c_sub(Xt[(rr + 1) * N + m], x0);
-      const float2 te = c_sub(Dt[(rr + 1) * N + m], e0);
-      cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
-    }
-    if (m + 1 < N) {
-      const float2 tx = c_sub(Xt[rr * N + m + 1], x0);
-      const float2 te = c_sub(Dt[rr * N + m + 1], e0);
-      cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
-    }
-  }
-  // Phase C: row FFTs of d_new.
-  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
-  const int n = n0 + team;
-  float2 val[8];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int p = t + e * S::T;
-    val[e] = (n < N && p < N) ? Dt[team * N + p] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();  // LDS tiles are reused as FFT buffers below
-  fft_team<L, false, true>(val, t, team_buf0<L>(sh, team), team_buf1<L>(sh, team), tw);
-  if (n < N) {
-    float2* out = T + ((size_t)f * N + n) * L;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) out[t + e * S::T] = val[e];
-  }
-  double v2[2] = {gd, cv};
-  block_sum<2>(v2, red);
-  if (threadIdx.x == 0) {
-    double* o = p1 + ((size_t)f * gridDim.x + blockIdx.x) * 2;
-    o[0] = v2[0];
-    o[1] = v2[1];
-  }
-}
-
 // ---------------------------------------------------------------- column pass
 // Block = COLS columns of frame f, THREADS threads (TEAMS = THREADS / (L/8)
 // columns transformed at once).  With p3 != NULL the block also writes the
@@ -198,10 +99,22 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* _
   const int q0 = blockIdx.x * COLS;
   float2* Tf = T + (size_t)f * N * L;
   double dqd = 0.0;
-  load_twiddles<L>(tw, twg);
-  for (int i = threadIdx.x; i < N * COLS; i += NT) {
+  // Stage the block's columns: every load of a thread is issued before the
+  // first LDS store (static count: N <= L/2).
+  constexpr int SMAX = (L / 2) * COLS / NT;
+  float2 stg[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
     const int n = i / COLS, c = i - n * COLS;
-    tile[c * TS + n] = Tf[(size_t)n * L + q0 + c];
+    stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
+  }
+  load_twiddles<L>(tw, twg);
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
+    const int n = i / COLS, c = i - n * COLS;
+    if (n < N) tile[c * TS + n] = stg[s];
   }
   __syncthreads();
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
@@ -241,9 +154,11 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* _
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N * COLS; i += NT) {
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
     const int n = i / COLS, c = i - n * COLS;
-    Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
+    if (n < N) Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
   }
   if (p3) {
     double v1[1] = {dqd};
@@ -326,25 +241,6 @@ hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
                           const float2* tw, const FrameParam* fp, int k, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
   RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, tw, fp, k)));
-  return hipGetLastError();
-}
-
-hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* g,
-                             const float2* d_old, float2* d_new,
-                             const float2* x, float2* T, const double* p4,
-                             int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, int k, hipStream_t s) {
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-#define RECON_DIR(PHI_)                                                       \
-  RECON_L_SWITCH(L, (k_dir_rowfft<LL, PHI_><<<grid, 256, 0, s>>>(             \
-                        N, g, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k)))
-  switch (phi) {
-    case 0: RECON_DIR(0); break;
-    case 1: RECON_DIR(1); break;
-    case 2: RECON_DIR(2); break;
-    default: return hipErrorInvalidValue;
-  }
-#undef RECON_DIR
   return hipGetLastError();
 }
 
