@@ -34,6 +34,10 @@ struct FftShape {
   static constexpr int REM = LOG % 3;
   static constexpr int NP = NR8 + (REM ? 1 : 0);
   static constexpr int PAD = L + L / 8;  // padded LDS entries per buffer
+  // Span of the first radix-8 pass that needs twiddles; the pass of span NS
+  // finds W^{r k} (r = 1..7, k < NS) at tw[NS - S0 + (r - 1) NS + k].
+  static constexpr int S0 = REM ? (1 << REM) : 8;
+  static constexpr int TWN = L - S0;  // entries of the per-pass twiddle table
 };
 
 // LDS index padding: one spare slot every 8 entries breaks the stride-8
@@ -125,10 +129,12 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[8], int t, const float2* tw
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
     if constexpr (NS > 1) {
-      constexpr int STEP = L / (NS * R);
+      // Per-pass table: consecutive k are consecutive entries, so a wave's
+      // twiddle reads are conflict-free (or broadcasts when NS < 64).
+      constexpr int OFF = NS - FftShape<L>::S0;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * STEP];
+        float2 w = tw[OFF + (r - 1) * NS + k];
         if (INV) w.y = -w.y;
         a[r] = c_mul(a[r], w);
       }
@@ -188,8 +194,8 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
 // Full transform.  For L > 512 every thread of the block must call this
 // (block barriers); for L <= 512 only the team's own wavefront is involved.
 // buf0/buf1: this team's LDS buffers of PAD entries (buf1 unused when the
-// team is wave-local; it may then alias buf0); tw: LDS table
-// tw[i] = exp(-2 pi i i / L), i < L.
+// team is wave-local; it may then alias buf0); tw: the per-pass LDS twiddle
+// table built by load_twiddles.
 template <int L, bool INV, bool HALF_IN>
 __device__ __forceinline__ void fft_team(float2 (&v)[8], int t, float2* buf0,
                                          float2* buf1, const float2* tw) {
@@ -206,10 +212,21 @@ constexpr int fft_team_lds() {
   return (FftSync<L>::WAVE_LOCAL ? 1 : 2) * FftShape<L>::PAD;
 }
 
-// Copy the plan's twiddle table (global) into LDS.
+// Build the per-pass twiddle table in LDS (TWN <= L entries) from the plan's
+// table g[i] = exp(-2 pi i i / L): entry NS - S0 + (r - 1) NS + k of the pass
+// of span NS holds g[r k L / (8 NS)].
 template <int L>
 __device__ __forceinline__ void load_twiddles(float2* tw, const float2* __restrict__ g) {
-  for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = g[i];
+  using S = FftShape<L>;
+  for (int i = threadIdx.x; i < S::TWN; i += blockDim.x) {
+    int ns = S::S0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      if (i >= 8 * ns - S::S0) ns *= 8;
+    const int q = i - (ns - S::S0);
+    const int r = q / ns + 1, k = q - (r - 1) * ns;
+    tw[i] = g[r * k * (L / (8 * ns))];
+  }
 }
 
 }  // namespace recon

@@ -34,6 +34,20 @@ struct RowCfg {
   static constexpr int EPT = W / TT;      // own pixels per thread (4)
 };
 
+// Logical (row block, frame) of this workgroup.  Workgroups are dispatched
+// round-robin over the 8 XCDs (linear id w runs on XCD w % 8); each XCD is
+// given a contiguous range of logical tiles, so neighbouring row blocks of a
+// frame, which read each other's rows as stencil halos, share one L2.
+__device__ __forceinline__ void xcd_tile(int& bx, int& f) {
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int w = blockIdx.x + blockIdx.y * nbx;
+  const int per = total / 8, rem = total % 8;
+  const int x = w % 8, i = w / 8;
+  const int logical = x * per + (x < rem ? x : rem) + i;
+  bx = logical % nbx;
+  f = logical / nbx;
+}
+
 // g = 2 r + lam * div, as every kernel forms it.
 __device__ __forceinline__ float2 grad_from(float2 r, float2 div, float lam) {
   return make_float2(fmaf(lam, div.x, 2.f * r.x), fmaf(lam, div.y, 2.f * r.y));
@@ -52,16 +66,19 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   constexpr int DT = (ROWS + 1) * W;      // d rows n0 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L>();
   constexpr int SH = (XT + DT > FFTB) ? XT + DT : FFTB;
+  // halo element j of a thread: row j / W, column j % W (W a power of two)
   constexpr int HX = (3 * W + 255) / 256;  // x halo elements per thread (3 rows)
   constexpr int HD = (W + 255) / 256;      // r, d halo elements per thread (1 row)
-  if (kit >= fp[blockIdx.y].stop_at) return;  // frame idle in this iteration (block-uniform)
+  int bx, f;
+  xcd_tile(bx, f);
+  if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
   __shared__ float2 tw[L];
   __shared__ float2 sh[SH];
   __shared__ double red[2 * 4];
+  __shared__ float sbeta;
   float2* Xt = sh;       // tile row i <-> image row n0 - 1 + i (stride N)
   float2* Dt = sh + XT;  // tile row i <-> image row n0 + i
-  const int f = blockIdx.y;
-  const int n0 = blockIdx.x * ROWS;
+  const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
   const int n = n0 + team;
@@ -81,9 +98,9 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
-    const int sel = j / N, m = j - sel * N;  // sel 0: n0-1, 1: n0+ROWS, 2: n0+ROWS+1
+    const int sel = j / W, m = j % W;  // sel 0: n0-1, 1: n0+ROWS, 2: n0+ROWS+1
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS + sel - 1;
-    const bool ok = j < 3 * N && img >= 0 && img < N;
+    const bool ok = j < 3 * W && m < N && img >= 0 && img < N;
     hx[s] = x[ok ? fo + (size_t)img * N + m : 0];
   }
 #pragma unroll
@@ -98,15 +115,18 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 
   // beta of the Polak-Ribiere (PR+) correction, with restart, from the
   // update kernel's partials [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
-  const double* pf = p4 + (size_t)f * nb4 * 4;
-  const double gg = wave_sum_partials(pf + 0, nb4, 4);
-  const double ggo = wave_sum_partials(pf + 1, nb4, 4);
-  const double gdo = wave_sum_partials(pf + 2, nb4, 4);
-  const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
-  double beta = 0.0;
-  if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
-  if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
-  const float bf = (float)beta;
+  // (one wavefront reduces, the block reads the value after the next barrier)
+  if (threadIdx.x < 64) {
+    const double* pf = p4 + (size_t)f * nb4 * 4;
+    const double gg = wave_sum_partials(pf + 0, nb4, 4);
+    const double ggo = wave_sum_partials(pf + 1, nb4, 4);
+    const double gdo = wave_sum_partials(pf + 2, nb4, 4);
+    const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+    double beta = 0.0;
+    if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
+    if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
+    if (threadIdx.x == 0) sbeta = (float)beta;
+  }
   const float lam = fp[f].lam, delta = fp[f].delta;
 
   // -- x tile
@@ -118,23 +138,27 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
-    const int sel = j / N, m = j - sel * N;
+    const int sel = j / W, m = j % W;
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS + sel - 1;
-    if (j < 3 * N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
+    if (j < 3 * W && m < N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
   }
   __syncthreads();
+  const float bf = sbeta;
 
   // -- gradient and new direction: own rows and the halo row n0 + ROWS
   double gd = 0.0;
   float2 dn[EPT];
+  float wdn[EPT], wrt[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
     dn[e] = zero;
+    wdn[e] = wrt[e] = 0.f;
     if (n < N && m < N) {
       const float2* mid = Xt + (team + 1) * N;
-      const float2 div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
-                                         n + 1 < N ? mid + N : nullptr, m, N, delta);
+      const float2 div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                            n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
+                                            wrt[e]);
       const float2 g = grad_from(ro[e], div, lam);
       dn[e] = make_float2(fmaf(bf, dv[e].x, -g.x), fmaf(bf, dv[e].y, -g.y));
       Dt[team * N + m] = dn[e];
@@ -164,23 +188,22 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
     if (n < N && m < N) {
-      const float2 x0 = Xt[(team + 1) * N + m], e0 = Dt[team * N + m];
+      // the weights of the pixel's forward edges come from the divergence
+      const float2 e0 = Dt[team * N + m];
       if (n + 1 < N) {
-        const float2 tx = c_sub(Xt[(team + 2) * N + m], x0);
         const float2 te = c_sub(Dt[(team + 1) * N + m], e0);
-        cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+        cv += (double)wdn[e] * (double)c_abs2(te);
       }
       if (m + 1 < N) {
-        const float2 tx = c_sub(Xt[(team + 1) * N + m + 1], x0);
         const float2 te = c_sub(Dt[team * N + m + 1], e0);
-        cv += (double)pen_weight<PHI>(c_abs2(tx), delta) * (double)c_abs2(te);
+        cv += (double)wrt[e] * (double)c_abs2(te);
       }
     }
   }
   double v2[2] = {gd, cv};
   block_sum<2>(v2, red);  // ends with a block barrier: the tiles are free
   if (threadIdx.x == 0) {
-    double* o = p1 + ((size_t)f * gridDim.x + blockIdx.x) * 2;
+    double* o = p1 + ((size_t)f * gridDim.x + bx) * 2;
     o[0] = v2[0];
     o[1] = v2[1];
   }
@@ -213,15 +236,17 @@ __global__ __launch_bounds__(256) void k_update(
   constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L>();
   constexpr int SH = (2 * XT > FFTB) ? 2 * XT : FFTB;
-  constexpr int HX = (2 * W + 255) / 256;  // halo elements per thread (2 rows)
-  if (kit >= fp[blockIdx.y].stop_at) return;
+  constexpr int HX = (2 * W + 255) / 256;  // halo elements per thread (2 rows, j -> j/W, j%W)
+  int bx, f;
+  xcd_tile(bx, f);
+  if (kit >= fp[f].stop_at) return;
   __shared__ float2 tw[L];
   __shared__ float2 sh[SH];
   __shared__ double red[4 * 4];
+  __shared__ float salpha;
   float2* Xo = sh;       // x at the start of the iteration; row i <-> image row n0-1+i
   float2* Xn = sh + XT;  // x + alpha d
-  const int f = blockIdx.y;
-  const int n0 = blockIdx.x * ROWS;
+  const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
   const int n = n0 + team;
@@ -246,25 +271,29 @@ __global__ __launch_bounds__(256) void k_update(
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
-    const int sel = j / N, m = j - sel * N;  // sel 0: n0-1, 1: n0+ROWS
+    const int sel = j / W, m = j % W;  // sel 0: n0-1, 1: n0+ROWS
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
-    const bool ok = j < 2 * N && img >= 0 && img < N;
+    const bool ok = j < 2 * W && m < N && img >= 0 && img < N;
     const size_t idx = ok ? fo + (size_t)img * N + m : 0;
     hx[s] = x_old[idx];
     hd[s] = d[idx];
   }
   load_twiddles<L>(tw, twg);
 
-  // Step length: exact minimiser of the half-quadratic majorant along d.
-  const double* q1 = p1 + (size_t)f * nb1 * 2;
-  const double gd = wave_sum_partials(q1 + 0, nb1, 2);
-  const double cvv = wave_sum_partials(q1 + 1, nb1, 2);
-  const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
+  // Step length: exact minimiser of the half-quadratic majorant along d
+  // (one wavefront reduces, the block reads it after the barrier).
   const float lam = fp[f].lam, delta = fp[f].delta;
-  const double den = 2.0 * dqd + (double)lam * cvv;
-  const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
-  const float af = (float)alpha;
-  __syncthreads();  // twiddles
+  if (threadIdx.x < 64) {
+    const double* q1 = p1 + (size_t)f * nb1 * 2;
+    const double gd = wave_sum_partials(q1 + 0, nb1, 2);
+    const double cvv = wave_sum_partials(q1 + 1, nb1, 2);
+    const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
+    const double den = 2.0 * dqd + (double)lam * cvv;
+    const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
+    if (threadIdx.x == 0) salpha = (float)alpha;
+  }
+  __syncthreads();  // twiddles, step length
+  const float af = salpha;
 
   // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
   fft_team<L, true, false>(val, t, sh + team * fft_team_lds<L>(),
@@ -284,9 +313,9 @@ __global__ __launch_bounds__(256) void k_update(
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
-    const int sel = j / N, m = j - sel * N;
+    const int sel = j / W, m = j % W;
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
-    if (j < 2 * N && img >= 0 && img < N) {
+    if (j < 2 * W && m < N && img >= 0 && img < N) {
       const int o = (img - n0 + 1) * N + m;
       Xo[o] = hx[s];
       Xn[o] = make_float2(fmaf(af, hd[s].x, hx[s].x), fmaf(af, hd[s].y, hx[s].y));
@@ -320,7 +349,7 @@ __global__ __launch_bounds__(256) void k_update(
   }
   block_sum<4>(acc, red);
   if (threadIdx.x == 0) {
-    double* o = p4 + ((size_t)f * gridDim.x + blockIdx.x) * 4;
+    double* o = p4 + ((size_t)f * gridDim.x + bx) * 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) o[k] = acc[k];
   }

@@ -43,18 +43,39 @@ __device__ __forceinline__ float2 wdiff(float2 a, float2 b, float delta) {
 // (D^T (w . D x))[n][m] from a tile holding rows n-1, n, n+1 of x:
 // up/mid/dn point at column 0 of those rows (up/dn may be null at the image
 // border).  Vertical differences exist for rows 0..N-2, horizontal for
-// columns 0..N-2 (non-periodic).
+// columns 0..N-2 (non-periodic).  Also returns the weights of the pixel's
+// forward edges (down: (n, m)-(n+1, m), right: (n, m)-(n, m+1); 0 where the
+// edge does not exist), which the curvature of the majorant reuses.
+template <int PHI>
+__device__ __forceinline__ float2 divergence_fw(const float2* up, const float2* mid,
+                                                const float2* dn, int m, int N, float delta,
+                                                float& w_dn, float& w_rt) {
+  const float2 c = mid[m];
+  float2 acc = make_float2(0.f, 0.f);
+  w_dn = 0.f;
+  w_rt = 0.f;
+  if (up) acc = c_add(acc, wdiff<PHI>(up[m], c, delta));
+  if (dn) {
+    const float2 t = c_sub(dn[m], c);
+    w_dn = pen_weight<PHI>(c_abs2(t), delta);
+    acc = c_sub(acc, c_scale(t, w_dn));
+  }
+  if (m > 0) acc = c_add(acc, wdiff<PHI>(mid[m - 1], c, delta));
+  if (m + 1 < N) {
+    const float2 t = c_sub(mid[m + 1], c);
+    w_rt = pen_weight<PHI>(c_abs2(t), delta);
+    acc = c_sub(acc, c_scale(t, w_rt));
+  }
+  return acc;
+}
+
+// The same without the weights (one code path, so the same values).
 template <int PHI>
 __device__ __forceinline__ float2 divergence(const float2* up, const float2* mid,
                                              const float2* dn, int m, int N,
                                              float delta) {
-  const float2 c = mid[m];
-  float2 acc = make_float2(0.f, 0.f);
-  if (up) acc = c_add(acc, wdiff<PHI>(up[m], c, delta));
-  if (dn) acc = c_sub(acc, wdiff<PHI>(c, dn[m], delta));
-  if (m > 0) acc = c_add(acc, wdiff<PHI>(mid[m - 1], c, delta));
-  if (m + 1 < N) acc = c_sub(acc, wdiff<PHI>(c, mid[m + 1], delta));
-  return acc;
+  float w_dn, w_rt;
+  return divergence_fw<PHI>(up, mid, dn, m, N, delta, w_dn, w_rt);
 }
 
 }  // namespace recon
