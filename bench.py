@@ -43,24 +43,60 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def colpass_bytes(N: int, L: int, B: int) -> float:
-    """Algorithmic HBM bytes of one column-pass launch over B frames:
-    read and write the N x L complex64 intermediate per frame (16 N L bytes)
-    and read the L x L FP32 spectrum once (4 L^2)."""
-    return B * 16.0 * N * L + 4.0 * L * L
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16x3": 2500.0, "bf16x3": 2500.0}
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+CSRC = os.path.join(ROOT, "paper_0908_3252_amd", "csrc")
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
 def kernel_bytes(kind: str, N: int, L: int, B: int) -> float:
-    img = 8.0 * N * N  # one complex64 image
-    if kind == "colpass":
-        return colpass_bytes(N, L, B)
-    if kind == "dir_rowfft":   # read g, d_old, x; write d, T (N x L)
-        return B * (3 * img + img + 8.0 * N * L)
-    if kind == "rowifft":      # read T; write Qd
-        return B * (8.0 * N * L + img)
-    if kind == "update":       # read x, d, r, Qd, g; write x, r, g
-        return B * 8 * img
+    """Algorithmic HBM bytes of one launch over B frames (each array moved
+    once; stencil halo re-reads are not counted)."""
+    img = 8.0 * N * N          # one complex64 image
+    tmat = 8.0 * N * L         # the N x L complex64 intermediate of one frame
+    if kind == "colpass":      # read and write the intermediate, read the spectrum once
+        return B * 2 * tmat + 4.0 * L * L
+    if kind == "dir_rowfft":   # read x, r, d_old; write d, intermediate
+        return B * (4 * img + tmat)
+    if kind == "update":       # read intermediate, x, d, r; write x, r
+        return B * (tmat + 5 * img)
     raise ValueError(kind)
+
+
+def kernel_flops(kind: str, N: int, M: int, L: int, B: int) -> float:
+    """Algorithmic flops of one launch over B frames."""
+    if kind in ("adjoint", "forward"):  # complex MAC = 8 real flops, N^2 M per frame
+        return 8.0 * N * N * M * B
+    if kind == "colpass":  # two length-L FFTs per column (5 L log2 L) + the real scaling
+        return B * L * (2 * 5.0 * L * np.log2(L) + 6.0 * L)
+    raise ValueError(kind)
+
+
+def csrc_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kind: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
+    what the counter reads for a plain copy of known size), or None when the
+    kernel sources have changed since the counters were taken."""
+    path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 7 and f[0] == "traffic" and f[1] == kind:
+            fetch_kib, write_kib, ffac, wfac, dig = map(str, f[2:])
+            if dig != digest:
+                return None
+            return round((float(fetch_kib) * float(ffac) + float(write_kib) * float(wfac)) * 1024.0)
+    return None
 
 
 def synth_batch(plan, prob, B, torch):
@@ -144,8 +180,6 @@ def main():
     ap.add_argument("--workload", default="series256", choices=list(WORKLOADS))
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
-    ap.add_argument("--trace", default="colpass",
-                    choices=["colpass", "dir_rowfft", "rowifft", "update"])
     ap.add_argument("--prec", default="fp64", choices=list(PRECS),
                     help="NUDFT contraction precision (fp64: FP64-accumulated adjoint)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -217,7 +251,11 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
 
-    recon.trace_enable(args.trace, capacity=args.steps * iters + 16)
+    kinds = ["adjoint", "forward", "dir_rowfft", "colpass", "update"]
+    # events around the first 64 launches of each kind (every step's adjoint
+    # and forward, the first 64 iterations' kernels): enough for the averages
+    # without instrumenting every launch of the timed region
+    recon.trace_enable_set(kinds, capacity=max(args.steps, 64))
     times = []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -229,20 +267,44 @@ def main():
         log(f"step {i + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
-    kms = recon.trace_read()
+    kms = {k: recon.trace_read(kind=k) for k in kinds}
     recon.trace_enable(None)
     st = recon.stats_to_numpy(stats, B)
     ms_step = 1e3 * total / args.steps
     value = B * args.steps / total
 
-    # roofline of the traced kernel
-    kb = kernel_bytes(args.trace, N, L, B)
-    avg_ms = float(np.mean(kms)) if len(kms) else float("nan")
-    achieved = kb / (avg_ms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=args.trace, achieved=round(achieved, 1),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None, avg_launch_ms=round(avg_ms, 5), launches=int(len(kms)),
-                    algorithmic_bytes_per_launch=kb)
+    # rooflines of the traced kernels (HIP events on the solve stream)
+    digest = csrc_digest()
+    rooflines = {}
+    for k in kinds:
+        d = kms[k]
+        if not len(d):
+            continue
+        avg_ms = float(np.mean(d))
+        ent = dict(avg_launch_ms=round(avg_ms, 5), launches=int(len(d)),
+                   ms_per_step=round(float(np.sum(d)) / args.steps, 3))
+        if k in ("adjoint", "forward"):
+            fl = kernel_flops(k, N, M, L, B)
+            peak = MFMA_PEAK_TFLOPS[args.prec if k == "adjoint" else
+                                    ("fp32" if args.prec in ("fp32", "fp64") else args.prec)]
+            ach = fl / (avg_ms * 1e-3) / 1e12
+            ent.update(bound="mfma", achieved=round(ach, 2), peak=peak, unit="TFLOP/s",
+                       frac=round(ach / peak, 4), algorithmic_flops_per_launch=fl)
+        else:
+            kb = kernel_bytes(k, N, L, B)
+            ach = kb / (avg_ms * 1e-3) / 1e9
+            ent.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                       frac=round(ach / HBM_PEAK_GBS, 4), algorithmic_bytes_per_launch=kb)
+            if k == "colpass":
+                fl = kernel_flops(k, N, M, L, B)
+                ent["alu_fp32_tflops"] = round(fl / (avg_ms * 1e-3) / 1e12, 2)
+                ent["alu_frac_of_fp32_vector_peak"] = round(
+                    fl / (avg_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)
+        ent["traffic"] = measured_traffic(args.workload, k, digest)
+        rooflines[k] = ent
+    dominant = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"])
+    roofline = dict(rooflines[dominant])
+    roofline["kernel"] = dominant
 
     # single-frame latency (one 256^2 reconstruction, same hot path, B = 1)
     lat = []
@@ -291,6 +353,8 @@ def main():
         "single_frame_latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                     "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "roofline": roofline,
+        "rooflines": rooflines,
+        "csrc_digest": digest,
         "status_ok_frames": int(np.sum(st["status"] == 0)),
         "grad_ratio_median": float(np.median(st["grad_ratio"])),
     }

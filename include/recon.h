@@ -134,8 +134,8 @@ void recon_plan_destroy(recon_plan_t plan);
  * kernel.  Computes the lag kernel h[a][b] = (1/N^2) sum_l
  * exp(-i 2 pi (ky_l a + kx_l b)), a, b in [-(N-1), N-1] (h[a][b] is the
  * paper's G[-b][-a]) with FP64 MFMA accumulation over all samples, embeds it
- * circularly in L x L, takes its 2D FFT (FP32) and keeps the real spectrum
- * inside the plan.  Must be called once before recon_solve /
+ * circularly in L x L, takes its 2D FFT in FP64 and keeps the real spectrum
+ * (rounded once to FP32) inside the plan.  Must be called once before recon_solve /
  * recon_gram_apply.  ws: device scratch >= recon_gram_workspace_bytes.
  * Optional outputs (NULL to skip): khat_out device float32 [L][L] (p, q),
  * the unscaled real spectrum; lag_out device complex128 [2N-1][2N-1]
@@ -250,8 +250,9 @@ int64_t recon_pool_iteration(recon_plan_t plan, void* ws);
 
 /* Kernel timing trace (HIP events around every launch of one kernel kind on
  * the launching stream).  kernel: -1 = off, 0 = direction + row FFT,
- * 1 = column pass, 2 = inverse row FFT, 3 = CG update, 4 = adjoint
- * contraction, 5 = Gram contraction, 6 = forward contraction.  capacity
+ * 1 = column pass, 2 = inverse row FFT of recon_gram_apply, 3 = CG update
+ * (inverse row FFT + update), 4 = adjoint contraction (all launches of one
+ * recon_adjoint or solve), 5 = Gram contraction, 6 = forward contraction.  capacity
  * bounds the number of recorded launches (later ones are not recorded).
  * Creating the events allocates no device buffers.  recon_trace_read waits
  * for the recorded events and writes up to n durations (ms) to ms_out; it
@@ -259,6 +260,13 @@ int64_t recon_pool_iteration(recon_plan_t plan, void* ws);
  * not thread-safe against concurrent solves. */
 recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity);
 int32_t recon_trace_read(float* ms_out, int32_t n);
+/* Several kinds at once: bit k of `mask` enables kind k (as numbered above),
+ * each with its own `capacity` records; mask 0 turns tracing off.
+ * recon_trace_read_kind reads the durations of one enabled kind (0 if the
+ * kind is not enabled, -1 on error); recon_trace_read reads the lowest
+ * enabled kind. */
+recon_status_t recon_trace_enable_set(uint32_t mask, int32_t capacity);
+int32_t recon_trace_read_kind(int32_t kernel, float* ms_out, int32_t n);
 
 const char* recon_status_string(recon_status_t s);
 /* Detail of the last error on the calling thread ("" if none). */

@@ -148,25 +148,28 @@ GramWsLayout gram_ws_layout(int64_t M, int32_t N, int32_t L) {
   return g;
 }
 
-// Event trace of one kernel kind (recon_trace_enable).
+// Event traces of kernel kinds (recon_trace_enable / recon_trace_enable_set):
+// per kind, up to `capacity` pairs of events recorded around its launches.
+constexpr int TK_KINDS = 7;
 struct Trace {
   std::mutex mu;
-  int kernel = -1;
+  unsigned mask = 0;  // enabled kinds
+  int first = -1;     // kind read by recon_trace_read
   int capacity = 0;
-  int used = 0;
-  std::vector<hipEvent_t> ev;  // 2 per record
+  int used[TK_KINDS] = {};
+  std::vector<hipEvent_t> ev[TK_KINDS];  // 2 per record
 } g_trace;
 
 struct TraceScope {
   hipEvent_t stop = nullptr;
   hipStream_t s;
   TraceScope(int kernel, hipStream_t st) : s(st) {
-    if (g_trace.kernel != kernel) return;
+    if (!(g_trace.mask & (1u << kernel))) return;
     std::lock_guard<std::mutex> lk(g_trace.mu);
-    if (g_trace.kernel != kernel || g_trace.used >= g_trace.capacity) return;
-    const int i = g_trace.used++;
-    (void)hipEventRecord(g_trace.ev[2 * i], s);
-    stop = g_trace.ev[2 * i + 1];
+    if (!(g_trace.mask & (1u << kernel)) || g_trace.used[kernel] >= g_trace.capacity) return;
+    const int i = g_trace.used[kernel]++;
+    (void)hipEventRecord(g_trace.ev[kernel][2 * i], s);
+    stop = g_trace.ev[kernel][2 * i + 1];
   }
   ~TraceScope() {
     if (stop) (void)hipEventRecord(stop, s);
@@ -712,33 +715,70 @@ int64_t recon_pool_iteration(recon_plan_t p, void* ws) {
   return c.iters;
 }
 
-recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity) {
-  std::lock_guard<std::mutex> lk(g_trace.mu);
-  for (hipEvent_t e : g_trace.ev) (void)hipEventDestroy(e);
-  g_trace.ev.clear();
-  g_trace.used = 0;
-  g_trace.kernel = -1;
+static void trace_clear() {
+  for (auto& v : g_trace.ev) {
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    v.clear();
+  }
+  for (int& u : g_trace.used) u = 0;
+  g_trace.mask = 0;
+  g_trace.first = -1;
   g_trace.capacity = 0;
-  if (kernel < 0) return RECON_OK;
-  if (kernel > TK_FWD || capacity < 1) return fail(RECON_E_ARG, "bad trace request");
-  g_trace.ev.resize(2 * (size_t)capacity);
-  for (auto& e : g_trace.ev) HIP_TRY(hipEventCreate(&e));
+}
+
+recon_status_t recon_trace_enable_set(uint32_t mask, int32_t capacity) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  trace_clear();
+  if (mask == 0) return RECON_OK;
+  if ((mask >> TK_KINDS) != 0 || capacity < 1) return fail(RECON_E_ARG, "bad trace request");
+  for (int k = 0; k < TK_KINDS; ++k) {
+    if (!(mask & (1u << k))) continue;
+    g_trace.ev[k].resize(2 * (size_t)capacity);
+    for (auto& e : g_trace.ev[k]) {
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        e = nullptr;
+        trace_clear();
+        return hip_fail(err, "hipEventCreate");
+      }
+    }
+    if (g_trace.first < 0) g_trace.first = k;
+  }
   g_trace.capacity = capacity;
-  g_trace.kernel = kernel;
+  g_trace.mask = mask;
   return RECON_OK;
 }
 
-int32_t recon_trace_read(float* ms_out, int32_t n) {
+recon_status_t recon_trace_enable(int32_t kernel, int32_t capacity) {
+  if (kernel < 0) return recon_trace_enable_set(0, 0);
+  if (kernel >= TK_KINDS) return fail(RECON_E_ARG, "bad trace request");
+  return recon_trace_enable_set(1u << kernel, capacity);
+}
+
+int32_t recon_trace_read_kind(int32_t kernel, float* ms_out, int32_t n) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
-  if (!ms_out || n < 0) return -1;
-  const int m = g_trace.used < n ? g_trace.used : n;
+  if (!ms_out || n < 0 || kernel < 0 || kernel >= TK_KINDS) return -1;
+  if (!(g_trace.mask & (1u << kernel))) return 0;
+  const int m = g_trace.used[kernel] < n ? g_trace.used[kernel] : n;
+  const auto& ev = g_trace.ev[kernel];
   for (int i = 0; i < m; ++i) {
-    if (hipEventSynchronize(g_trace.ev[2 * i + 1]) != hipSuccess) return -1;
+    if (hipEventSynchronize(ev[2 * i + 1]) != hipSuccess) return -1;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, g_trace.ev[2 * i], g_trace.ev[2 * i + 1]) != hipSuccess) return -1;
+    if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) return -1;
     ms_out[i] = ms;
   }
   return m;
+}
+
+int32_t recon_trace_read(float* ms_out, int32_t n) {
+  int first;
+  {
+    std::lock_guard<std::mutex> lk(g_trace.mu);
+    first = g_trace.first;
+  }
+  if (first < 0) return (ms_out && n >= 0) ? 0 : -1;
+  return recon_trace_read_kind(first, ms_out, n);
 }
 
 const char* recon_status_string(recon_status_t s) {

@@ -69,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_pool_iteration": (i64, [vp, vp]),
         "recon_trace_enable": (i32, [i32, i32]),
         "recon_trace_read": (i32, [c.POINTER(c.c_float), i32]),
+        "recon_trace_enable_set": (i32, [c.c_uint32, i32]),
+        "recon_trace_read_kind": (i32, [i32, c.POINTER(c.c_float), i32]),
         "recon_status_string": (c.c_char_p, [i32]),
         "recon_last_error": (c.c_char_p, []),
         "recon_version": (c.c_char_p, []),
@@ -320,12 +322,22 @@ def trace_enable(kernel: Optional[str], capacity: int = 4096):
     _check(load().recon_trace_enable(-1 if kernel is None else TRACE[kernel], int(capacity)))
 
 
-def trace_read(n: int = 1 << 16) -> np.ndarray:
+def trace_read(n: int = 1 << 16, kind: Optional[str] = None) -> np.ndarray:
+    """Durations (ms) recorded for one kind (default: the lowest enabled)."""
     buf = (ctypes.c_float * n)()
-    m = load().recon_trace_read(buf, n)
+    lib = load()
+    m = lib.recon_trace_read(buf, n) if kind is None else lib.recon_trace_read_kind(TRACE[kind], buf, n)
     if m < 0:
         raise ReconError(E_HIP, "trace read failed")
     return np.array(buf[:m], dtype=np.float64)
+
+
+def trace_enable_set(kinds, capacity: int = 4096):
+    """Record events around the launches of several kinds at once."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << TRACE[k]
+    _check(load().recon_trace_enable_set(mask, int(capacity)))
 
 
 def stats_to_numpy(st, B: int) -> np.ndarray:
