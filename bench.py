@@ -281,8 +281,9 @@ def main():
         if not len(d):
             continue
         avg_ms = float(np.mean(d))
-        ent = dict(avg_launch_ms=round(avg_ms, 5), launches=int(len(d)),
-                   ms_per_step=round(float(np.sum(d)) / args.steps, 3))
+        per_step = 1 if k in ("adjoint", "forward") else iters  # launches per step
+        ent = dict(avg_launch_ms=round(avg_ms, 5), launches_timed=int(len(d)),
+                   ms_per_step=round(avg_ms * per_step, 3))
         if k in ("adjoint", "forward"):
             fl = kernel_flops(k, N, M, L, B)
             peak = MFMA_PEAK_TFLOPS[args.prec if k == "adjoint" else

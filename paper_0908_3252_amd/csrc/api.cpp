@@ -57,7 +57,7 @@ recon_status_t check_geometry(int64_t M, int32_t N, int32_t L) {
 }
 
 struct PlanLayout {
-  size_t k, ex, ey, tw, khat, at, xs, total;
+  size_t k, ex, ey, tw, khat, at, xs, ph, total;
 };
 
 PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
@@ -79,6 +79,11 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
     off = align_up(off + 4 * (size_t)N * split_pad_M(M) * 2);
     p.xs = off;
     off = align_up(off + 4 * (size_t)M * split_pad_N(N) * 2);
+  }
+  p.ph = 0;
+  if (prec == RECON_FP64) {  // phase tables of the FP64 adjoint
+    p.ph = off;
+    off = align_up(off + 2 * (size_t)M * phase_record(N) * sizeof(double2));
   }
   p.total = off;
   return p;
@@ -207,6 +212,7 @@ struct recon_plan_s {
   float* khat() const { return reinterpret_cast<float*>(mem + lay.khat); }
   void* at() const { return mem + lay.at; }
   void* xs() const { return mem + lay.xs; }
+  double2* ph() const { return reinterpret_cast<double2*>(mem + lay.ph); }
   bool split() const { return prec == RECON_BF16X3 || prec == RECON_FP16X3; }
   int table_prec() const { return prec; }
   bool has_tables() const { return split(); }
@@ -256,7 +262,7 @@ recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b,
     HIP_TRY(launch_adjoint_split(p->prec, p->M, p->N, B, p->at(), p->ex(), y, sc, b,
                                  static_cast<float2*>(part), s));
   else if (p->prec == RECON_FP64)
-    HIP_TRY(launch_adjoint_f64(p->M, p->N, B, p->k(), y, b, static_cast<double2*>(part), s));
+    HIP_TRY(launch_adjoint_f64(p->M, p->N, B, p->ph(), y, b, static_cast<double2*>(part), s));
   else
     HIP_TRY(launch_adjoint_f32(p->M, p->N, B, p->ex(), p->ey(), y, b, static_cast<float2*>(part), s));
   return RECON_OK;
@@ -322,6 +328,7 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   if (e == hipSuccess) e = launch_tables_f32(M, N, p->k(), p->ex(), p->ey(), s);
   if (e == hipSuccess && p->has_tables())
     e = launch_tables_split(p->table_prec(), M, N, p->k(), p->at(), p->xs(), s);
+  if (e == hipSuccess && prec == RECON_FP64) e = launch_phase_tables_f64(M, N, p->k(), p->ph(), s);
   // The host copies above read caller and local memory: finish before return.
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {

@@ -137,7 +137,11 @@ hipError_t launch_spectrum_f64(int L, double2* emb, double2* tmp, float* khat_s,
                                float* khat_out, hipStream_t s);
 // Adjoint accumulated in FP64 (phasors generated in FP64 from k); b FP32.
 // part: split-K partials, FP64 complex [splits][group][N][N].
-hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double* k, const float2* y,
+// FP64 phase tables of the accurate adjoint: phase_record(N) double2 per
+// sample and axis (unit step, in-tile offsets, tile bases), ph[2][M][R].
+int phase_record(int N);
+hipError_t launch_phase_tables_f64(int64_t M, int N, const double* k, double2* ph, hipStream_t s);
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
                               float2* b, double2* part, hipStream_t s);
 
 }  // namespace recon

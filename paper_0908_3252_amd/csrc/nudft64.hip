@@ -5,10 +5,15 @@
 //
 // The perturbation of b propagates into the iterate with a large gain (the
 // criterion is ill-conditioned), so this form keeps every phasor, product and
-// partial sum in FP64 and rounds b to FP32 once at the end.  Phasors are
-// generated on the fly from the exactly reduced FP64 phase: for four
-// consecutive indices j0..j0+3, exp(-i 2 pi k j0) and exp(-i 2 pi k) by
-// sincospi and three complex products (relative error ~1e-16).
+// partial sum in FP64 and rounds b to FP32 once at the end.
+//
+// Phasors come from per-plan FP64 phase tables, one record per sample and
+// axis: exp(-i 2 pi k) (unit step), exp(-i 2 pi k 4j) for j < 16 (offsets
+// inside a 64-wide tile) and exp(-i 2 pi k 64t) for the tiles t.  A thread
+// forms exp(-i 2 pi k (64t + 4j + v)), v < 4, as tile x offset followed by
+// three unit steps: four complex products instead of sincospi evaluations
+// (on this chip FP64 vector work competes with the FP64 matrix pipe), with a
+// relative error of a few 1e-16.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -23,9 +28,38 @@ __device__ __forceinline__ double2 z_mul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
+int phase_record(int N) { return 17 + (N + AT - 1) / AT; }
+
+// ph[a][l][r], a = 0 (k_x), 1 (k_y); r = 0: exp(-i 2 pi k), 1 + j:
+// exp(-i 2 pi k 4j) (j < 16), 17 + t: exp(-i 2 pi k AT t).  Every entry from
+// the exactly reduced FP64 phase.
+__global__ void k_phase_tables_f64(int64_t M, int R, const double* __restrict__ k,
+                                   double2* __restrict__ ph) {
+  const int64_t total = 2 * M * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t al = i / R;
+    const int r = (int)(i - al * R);
+    const int a = (int)(al / M);
+    const int64_t l = al - (int64_t)a * M;
+    const double kv = k[2 * l + a];
+    const double j = r == 0 ? 1.0 : (r <= 16 ? 4.0 * (r - 1) : (double)AT * (r - 17));
+    ph[i] = phasor_f64(-turn_frac(kv, j));
+  }
+}
+
+hipError_t launch_phase_tables_f64(int64_t M, int N, const double* k, double2* ph, hipStream_t s) {
+  const int R = phase_record(N);
+  int64_t blocks = (2 * M * R + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_phase_tables_f64<<<(int)blocks, 256, 0, s>>>(M, R, k, ph);
+  return hipGetLastError();
+}
+
 // grid: (n-tiles, m-tiles * frames, splits)
 __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, int splits,
-                                                     const double* __restrict__ k,
+                                                     const double2* __restrict__ ph,
+                                                     int R,
                                                      const float2* __restrict__ y,
                                                      double2* __restrict__ part,
                                                      float2* __restrict__ out, float scale) {
@@ -53,19 +87,18 @@ __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, in
     const bool lv = l < l_end;
     double2 ea[4], ez[4];
     if (lv) {
-      const double kx = k[2 * l + 0], ky = k[2 * l + 1];
+      const double2* rx = ph + (size_t)l * R;         // k_x record of sample l
+      const double2* ry = ph + ((size_t)M + l) * R;   // k_y record
       const float2 yv = yf[l];
       const double2 yd = make_double2(yv.x, yv.y);
       // conj(Ey[l][n]) = exp(-i 2 pi ky n), n = n0 + lc + v
-      double2 p = phasor_f64(-turn_frac(ky, (double)(n0 + lc)));
-      const double2 sy = phasor_f64(-turn_frac(ky, 1.0));
-      ea[0] = p;
+      const double2 sy = ry[0];
+      ea[0] = z_mul(ry[17 + n0 / AT], ry[1 + lc / 4]);
 #pragma unroll
       for (int v = 1; v < 4; ++v) ea[v] = z_mul(ea[v - 1], sy);
       // y_l conj(Ex[l][m]) = y_l exp(-i 2 pi kx m), m = m0 + lc + v
-      double2 q = phasor_f64(-turn_frac(kx, (double)(m0 + lc)));
-      const double2 sx = phasor_f64(-turn_frac(kx, 1.0));
-      double2 e = q;
+      const double2 sx = rx[0];
+      double2 e = z_mul(rx[17 + m0 / AT], rx[1 + lc / 4]);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (v) e = z_mul(e, sx);
@@ -142,19 +175,20 @@ __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __re
   }
 }
 
-hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double* k, const float2* y,
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
                               float2* b, double2* part, hipStream_t s) {
   const int sp = adjoint_splits(M, N);
+  const int R = phase_record(N);
   if (sp == 1) {
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * B, 1);
-    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, B, 1, k, y, nullptr, b, 1.0f / (float)N);
+    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, B, 1, ph, R, y, nullptr, b, 1.0f / (float)N);
     return hipGetLastError();
   }
   const int G = adjoint_group(M, N);
   for (int f0 = 0; f0 < B; f0 += G) {
     const int g = (B - f0 < G) ? B - f0 : G;
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * g, sp);
-    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, g, sp, k, y + (size_t)f0 * M, part, nullptr, 1.0f);
+    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, g, sp, ph, R, y + (size_t)f0 * M, part, nullptr, 1.0f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t count = (size_t)g * N * N;
