@@ -56,6 +56,27 @@ hipError_t launch_phase_tables_f64(int64_t M, int N, const double* k, double2* p
   return hipGetLastError();
 }
 
+// Phase-table records and datum of sample l for one thread: unit steps,
+// tile bases (tiles tn, tm) and in-tile offsets (index jo) of both axes.
+// Samples outside the split (l >= l_end, or an empty trailing split) read
+// sample 0 instead; the caller zeroes their contribution.
+__device__ __forceinline__ void adj_fetch(int64_t M, int R, const double2* __restrict__ ph,
+                                          const float2* __restrict__ yf, int64_t l,
+                                          int64_t l_end, int tn, int tm, int jo, double2& sy,
+                                          double2& ty, double2& oy, double2& sx, double2& tx,
+                                          double2& ox, float2& yv) {
+  const int64_t lc = l < l_end ? l : 0;
+  const double2* rx = ph + (size_t)lc * R;
+  const double2* ry = ph + ((size_t)M + lc) * R;
+  sy = ry[0];
+  ty = ry[17 + tn];
+  oy = ry[1 + jo];
+  sx = rx[0];
+  tx = rx[17 + tm];
+  ox = rx[1 + jo];
+  yv = yf[lc];
+}
+
 // grid: (n-tiles, m-tiles * frames, splits)
 __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, int splits,
                                                      const double2* __restrict__ ph,
@@ -82,23 +103,24 @@ __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, in
     for (int b = 0; b < 2; ++b) { cr[a][b] = v4d{0, 0, 0, 0}; ci[a][b] = v4d{0, 0, 0, 0}; }
 
   const int lr = tid >> 4, lc = (tid & 15) * 4;
+  // Stage inputs of this thread (sample l0 + lr), loaded one stage ahead so
+  // that the loads are in flight during the previous stage's products.
+  double2 sy, ty, oy, sx, tx, ox;
+  float2 yv;
+  adj_fetch(M, R, ph, yf, l_begin + lr, l_end, n0 / AT, m0 / AT, lc / 4, sy, ty, oy, sx, tx, ox,
+            yv);
   for (int64_t l0 = l_begin; l0 < l_end; l0 += AK) {
     const int64_t l = l0 + lr;
     const bool lv = l < l_end;
     double2 ea[4], ez[4];
-    if (lv) {
-      const double2* rx = ph + (size_t)l * R;         // k_x record of sample l
-      const double2* ry = ph + ((size_t)M + l) * R;   // k_y record
-      const float2 yv = yf[l];
+    {
       const double2 yd = make_double2(yv.x, yv.y);
       // conj(Ey[l][n]) = exp(-i 2 pi ky n), n = n0 + lc + v
-      const double2 sy = ry[0];
-      ea[0] = z_mul(ry[17 + n0 / AT], ry[1 + lc / 4]);
+      ea[0] = z_mul(ty, oy);
 #pragma unroll
       for (int v = 1; v < 4; ++v) ea[v] = z_mul(ea[v - 1], sy);
       // y_l conj(Ex[l][m]) = y_l exp(-i 2 pi kx m), m = m0 + lc + v
-      const double2 sx = rx[0];
-      double2 e = z_mul(rx[17 + m0 / AT], rx[1 + lc / 4]);
+      double2 e = z_mul(tx, ox);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (v) e = z_mul(e, sx);
@@ -114,6 +136,9 @@ __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, in
       Zi[lr][lc + v] = am ? ez[v].y : 0.0;
     }
     __syncthreads();
+    if (l0 + AK < l_end)
+      adj_fetch(M, R, ph, yf, l0 + AK + lr, l_end, n0 / AT, m0 / AT, lc / 4, sy, ty, oy, sx, tx,
+                ox, yv);
 #pragma unroll
     for (int kk = 0; kk < AK; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
