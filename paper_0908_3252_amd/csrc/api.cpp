@@ -90,7 +90,7 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
 }
 
 struct WsLayout {
-  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, sc, adj, total;
+  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, yyp, sc, adj, total;
   int rows, nb1, nb3, nb4, adj_splits;
 };
 
@@ -122,6 +122,7 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   w.pobj = take((size_t)B * w.nb4 * 3 * sizeof(double));
   w.params = take((size_t)B * sizeof(FrameParam));
   w.yy = take((size_t)B * sizeof(double));
+  w.yyp = take((size_t)B * sumsq_parts() * sizeof(double));
   w.sc = take((size_t)B * sizeof(float));
   w.adj_splits = adjoint_splits(M, N);
   {
@@ -380,7 +381,7 @@ recon_status_t recon_adjoint(recon_plan_t p, const float* y, int32_t B, float* b
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const float2* y2 = reinterpret_cast<const float2*>(y);
-  if (yy_out) HIP_TRY(launch_sumsq(p->M, B, y2, yy_out, s));
+  if (yy_out) HIP_TRY(launch_sumsq(p->M, B, y2, w.dbl(w.lay.yyp), yy_out, s));
   return adjoint_traced(p, y2, B, reinterpret_cast<float2*>(b), w.img(w.lay.adj),
                         reinterpret_cast<float*>(w.base + w.lay.sc), s);
 }
@@ -437,7 +438,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   double* yy = w.dbl(w.lay.yy);
   if (y) {
     const float2* y2 = reinterpret_cast<const float2*>(y);
-    HIP_TRY(launch_sumsq(p->M, B, y2, yy, s));
+    HIP_TRY(launch_sumsq(p->M, B, y2, w.dbl(w.lay.yyp), yy, s));
     recon_status_t r = adjoint_traced(p, y2, B, b, w.img(w.lay.adj),
                                       reinterpret_cast<float*>(w.base + w.lay.sc), s);
     if (r != RECON_OK) return r;
@@ -651,7 +652,8 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, fl
   const size_t fo = (size_t)slot * N * N;
   const int k = c.iters;
   const float2* y2 = reinterpret_cast<const float2*>(y);
-  HIP_TRY(launch_sumsq(p->M, 1, y2, w.dbl(w.lay.yy) + slot, s));
+  HIP_TRY(launch_sumsq(p->M, 1, y2, w.dbl(w.lay.yyp) + (size_t)slot * sumsq_parts(),
+                       w.dbl(w.lay.yy) + slot, s));
   st = adjoint_traced(p, y2, 1, w.img(w.lay.b) + fo, w.img(w.lay.adj),
                       reinterpret_cast<float*>(w.base + w.lay.sc) + slot, s);
   if (st != RECON_OK) return st;

@@ -99,7 +99,10 @@ hipError_t launch_adjoint_f32(int64_t M, int N, int B, const float2* ex,
 hipError_t launch_forward_f32(int64_t M, int N, int B, const float2* ex,
                               const float2* ey, const float2* x, float2* y,
                               hipStream_t s);
-hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* yy,
+// ||y_f||^2 per frame (FP64, fixed order); part: scratch of
+// sumsq_parts() doubles per frame.
+int sumsq_parts();
+hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* part, double* yy,
                         hipStream_t s);
 
 // ---- split-precision NUDFT (BF16 x3 / FP16 x3) ------------------------------

@@ -309,16 +309,28 @@ __global__ __launch_bounds__(256) void k_forward_f32(int64_t M, int N,
   }
 }
 
-__global__ void k_sumsq(int64_t M, const float2* __restrict__ y, double* __restrict__ yy) {
+// ||y_f||^2 in two fixed-order stages: block (s, f) sums chunk s of frame f
+// into part[f][s]; the finisher sums the SUMSQ_PARTS partials of a frame.
+constexpr int SUMSQ_PARTS = 64;
+
+__global__ void k_sumsq(int64_t M, int64_t chunk, const float2* __restrict__ y,
+                        double* __restrict__ part) {
   __shared__ double red[4];
-  const int f = blockIdx.x;
+  const int s = blockIdx.x, f = blockIdx.y;
+  const int64_t lo = (int64_t)s * chunk;
+  const int64_t hi = lo + chunk < M ? lo + chunk : M;
   double acc[1] = {0.0};
-  for (int64_t l = threadIdx.x; l < M; l += blockDim.x) {
+  for (int64_t l = lo + threadIdx.x; l < hi; l += blockDim.x) {
     const float2 v = y[(size_t)f * M + l];
     acc[0] += (double)v.x * v.x + (double)v.y * v.y;
   }
   block_sum<1>(acc, red);
-  if (threadIdx.x == 0) yy[f] = acc[0];
+  if (threadIdx.x == 0) part[(size_t)f * SUMSQ_PARTS + s] = acc[0];
+}
+
+__global__ void k_sumsq_finish(const double* __restrict__ part, double* __restrict__ yy) {
+  const double v = wave_sum_partials(part + (size_t)blockIdx.x * SUMSQ_PARTS, SUMSQ_PARTS, 1);
+  if (threadIdx.x == 0) yy[blockIdx.x] = v;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -387,8 +399,15 @@ hipError_t launch_forward_f32(int64_t M, int N, int B, const float2* ex, const f
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* yy, hipStream_t s) {
-  k_sumsq<<<B, 256, 0, s>>>(M, y, yy);
+int sumsq_parts() { return SUMSQ_PARTS; }
+
+hipError_t launch_sumsq(int64_t M, int B, const float2* y, double* part, double* yy,
+                        hipStream_t s) {
+  const int64_t chunk = (M + SUMSQ_PARTS - 1) / SUMSQ_PARTS;
+  k_sumsq<<<dim3(SUMSQ_PARTS, B), 256, 0, s>>>(M, chunk, y, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sumsq_finish<<<B, 64, 0, s>>>(part, yy);
   return hipGetLastError();
 }
 

@@ -511,22 +511,33 @@ def make_workload(count: int, seed: int = 4):
     return base, traj, plans
 
 
+PRECS = {"fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
+
+
 def serve(rate: float, workload, warmup_frac: float = 0.1, hbm_budget: Optional[int] = None,
-          chunk: int = 25, streams: int = 4, verify: int = 3, seed: int = 4, log=None) -> dict:
-    """Serve the workload's requests arriving at `rate` req/s on the GPU;
-    returns throughput, p50/p99 latency (warm-up requests excluded) and a
-    check that `verify` served results equal standalone solves bitwise."""
+          chunk: int = 25, streams: int = 4, verify: int = 3, seed: int = 4, prec: str = "fp64",
+          reference: Optional[Dict[int, Any]] = None, keep_results: bool = False,
+          log=None) -> dict:
+    """Serve the workload's requests arriving at `rate` req/s on the GPU with
+    plans of precision `prec`; returns throughput, p50/p99 latency (warm-up
+    requests excluded), a check that `verify` served results equal
+    standalone solves bitwise and, given `reference` (request id -> image of
+    another run), the relative L2 distance of every result to it."""
     import numpy as np
     import torch
     base, traj, plans = workload
     reqs = [Request(id=b["id"], arrival=b["arrival"] / rate, key=b["key"], y=b["y"],
                     lam=b["lam"], delta=b["delta"], iters=b["iters"]) for b in base]
-    ex = GpuExecutor(traj, streams=streams)
-    for key, plan in plans.items():
-        ex.keep_plan(key, plan)
+    ex = GpuExecutor(traj, prec=PRECS[prec], streams=streams)
+    if PRECS[prec] == ex.recon.FP64:
+        for key, plan in plans.items():
+            ex.keep_plan(key, plan)
+    else:  # plans of this precision, built before the clock starts
+        for key in traj:
+            ex.keep_plan(key, ex.build_plan(key))
     if hbm_budget is None:
         free, _total = torch.cuda.mem_get_info()
-        hbm_budget = int(0.8 * free) + sum(ex.plan_bytes(k) for k in plans)
+        hbm_budget = int(0.8 * free) + sum(ex.plan_bytes(k) for k in ex.plans)
     sched = Scheduler(ex, hbm_budget, slots=default_slots, chunk=chunk)
     sched.submit(reqs)
     sched.start()
@@ -535,7 +546,7 @@ def serve(rate: float, workload, warmup_frac: float = 0.1, hbm_budget: Optional[
     torch.cuda.synchronize()
     t_first = sorted(r.arrival for r in reqs)[int(warmup_frac * len(reqs))] if reqs else 0.0
     out = summarize(done, t_first)
-    out.update(rate=rate, requests=len(reqs), plans_built=sched.plans_built,
+    out.update(rate=rate, prec=prec, requests=len(reqs), plans_built=sched.plans_built,
                plans_evicted=sched.plans_evicted, chunk=chunk, streams=streams)
     st = [r for r in done if r.state == "done"]
     ok = 0
@@ -555,11 +566,25 @@ def serve(rate: float, workload, warmup_frac: float = 0.1, hbm_budget: Optional[
             torch.cuda.synchronize()
             same += int(torch.equal(x1[0].view(torch.float32), r.x.view(torch.float32)))
         out["bitwise_equal_standalone"] = f"{same}/{len(pick)}"
+    if reference is not None:
+        errs = []
+        for r in st:
+            xr = reference.get(r.id)
+            if xr is not None:
+                errs.append(float(torch.linalg.vector_norm(r.x - xr) /
+                                  torch.linalg.vector_norm(xr)))
+        if errs:
+            out["rel_l2_vs_reference"] = {"median": float(np.median(errs)),
+                                          "p99": float(np.percentile(errs, 99)),
+                                          "max": float(np.max(errs)), "n": len(errs)}
+    results = {r.id: r.x for r in st} if keep_results else None
     for r in reqs:  # release result buffers
-        r.x = r.stats = None
+        r.stats = None
+        if not keep_results:
+            r.x = None
     if log:
-        log(f"rate {rate}: {out}")
-    return out
+        log(f"rate {rate} prec {prec}: {out}")
+    return (out, results) if keep_results else out
 
 
 def main(argv=None):
@@ -568,6 +593,9 @@ def main(argv=None):
     import sys
     ap = argparse.ArgumentParser(description="continuous-batching reconstruction server")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000")
+    ap.add_argument("--precs", default="fp64",
+                    help="comma list of NUDFT precisions (fp64, fp32, fp16x3, bf16x3); with "
+                         "several, each later one is compared with the first's results")
     ap.add_argument("--count", type=int, default=2200)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=25)
@@ -579,10 +607,19 @@ def main(argv=None):
 
     log(f"synthesising {args.count} requests")
     wl = make_workload(args.count, args.seed)
+    precs = args.precs.split(",")
     res = []
     for rate in [float(r) for r in args.rates.split(",")]:
-        res.append(serve(rate, wl, chunk=args.chunk, streams=args.streams, seed=args.seed,
-                         log=log))
+        ref = None
+        for i, prec in enumerate(precs):
+            if len(precs) > 1 and i == 0:
+                out, ref = serve(rate, wl, chunk=args.chunk, streams=args.streams,
+                                 seed=args.seed, prec=prec, keep_results=True, log=log)
+            else:
+                out = serve(rate, wl, chunk=args.chunk, streams=args.streams, seed=args.seed,
+                            prec=prec, reference=ref, log=log)
+            res.append(out)
+        ref = None
     print(json.dumps({"serving": res}), flush=True)
 
 

@@ -127,3 +127,40 @@ def test_large_end_to_end_short(large):
               f"J rel diff {dj:.2e}", flush=True)
         assert e < bound
         assert dj < 10 * bound
+
+
+# Serving-size adjoints in every precision mode (batch 1, as admitted into a
+# slot pool), on sampled entries.  FP32-accumulating modes (FP32, split
+# FP16 x3) lose ~eps_32 sqrt(K) over the K samples one split-K block sums, so
+# their bound is 2e-6 (the bar at K = 512, the 256^2 workload) scaled by
+# sqrt(K / 512); split BF16 x3 is bounded by its ~16-bit products; FP64
+# accumulation by one FP32 rounding.
+def samples_per_split(M, N):
+    tiles = (-(-N // 64)) ** 2
+    sp = min(-(-1024 // tiles), max(1, (M + 127) // 128), 64)
+    return M / sp
+
+
+def serving_adj_tol(prec, M, N):
+    acc32 = 2e-6 * max(1.0, (samples_per_split(M, N) / 512) ** 0.5)
+    return {recon.FP64: 1e-7, recon.FP32: acc32, recon.FP16X3: acc32,
+            recon.BF16X3: max(2e-5, acc32)}[prec]
+
+
+@pytest.mark.parametrize("prec", [recon.FP64, recon.FP32, recon.FP16X3, recon.BF16X3])
+@pytest.mark.parametrize("N,I", [(64, 16), (192, 8), (384, 32)])
+def test_serving_size_adjoint_sampled(N, I, prec):
+    S = N * N // 16
+    k = synthetic.spiral_trajectory(N, I, S, 2.0)
+    print(f"adjoint N={N} M={k.shape[0]} prec={prec}", flush=True)
+    plan = recon.Plan(k, N, prec=prec)
+    rng = np.random.default_rng(N + 7 * I)
+    y = rand_c(rng, 1, k.shape[0]).astype(np.complex64)
+    b = host(plan.adjoint(dev(y)))[0]
+    n = np.concatenate([[0, N - 1, 0, N - 1], rng.integers(0, N, 60)])
+    m = np.concatenate([[0, N - 1, N - 1, 0], rng.integers(0, N, 60)])
+    ref = oracle.adjoint_at(y[0].astype(np.complex128), k, N, n, m)
+    e = rel(b[n, m], ref)
+    tol = serving_adj_tol(prec, k.shape[0], N)
+    print(f"  64 sampled entries: rel {e:.2e} (bound {tol:.1e})")
+    assert e < tol
