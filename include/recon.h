@@ -73,9 +73,19 @@ typedef enum {
   RECON_FP32 = 0,         /* FP32 operands, FP32 MFMA, FP32 accumulation */
   RECON_BF16X3 = 1,       /* split bf16 hi+lo operands, 3 products, FP32 acc. */
   RECON_FP16X3 = 2,       /* split fp16 hi+lo operands, 3 products, FP32 acc. */
-  RECON_FP64 = 3          /* adjoint with FP64 phasors, products and MFMA
+  RECON_FP64 = 3,         /* adjoint with FP64 phasors, products and MFMA
                              accumulation, rounded to FP32 once (accurate
                              form); the forward model stays FP32 */
+  /* Flag OR'ed into RECON_FP64: run the iteration of recon_solve and of the
+   * slot pools in FP64 (b, x, r, d, the row-transform intermediate, the
+   * FFTs, the penalty stencil and the Gram spectrum; b is not rounded to
+   * FP32).  The iterate after a fixed budget of iterations can amplify
+   * per-step rounding by orders of magnitude when the minimisation is far
+   * from converged; this form keeps it at FP64 level.  Inputs and outputs
+   * (y, x0, x, exported fields) stay complex64.  Requires L <= 1024; the
+   * workspace (recon_workspace_bytes with the same prec) is about twice as
+   * large.  recon_gram_apply, recon_adjoint and recon_forward are unchanged. */
+  RECON_ITER_FP64 = 16
 } recon_prec_t;
 
 /* Penalty phi(s), s = |difference| (Section 3.3). */
@@ -94,8 +104,8 @@ typedef struct {
   int32_t status;      /* RECON_OK or RECON_E_NONFINITE */
 } recon_stats_t;
 
-/* Supported ranges: 2 <= N <= 1024, L a power of two with 2N-1 <= L <= 2048,
- * 64 <= L, 1 <= M <= 2^31-1, 1 <= B. */
+/* Supported ranges: 2 <= N <= 1024, L a power of two with 2N-1 <= L <= 2048
+ * (L <= 1024 with RECON_ITER_FP64), 64 <= L, 1 <= M <= 2^31-1, 1 <= B. */
 
 /* ---- sizes (host only, no device work) ---------------------------------- */
 
@@ -108,8 +118,10 @@ size_t recon_plan_bytes(int64_t M, int32_t N, int32_t L, int32_t prec);
 size_t recon_gram_workspace_bytes(int64_t M, int32_t N, int32_t L);
 
 /* Bytes of device workspace for recon_solve / recon_gram_apply /
- * recon_adjoint / recon_forward on B frames of plan geometry (N, L, M). */
-size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B);
+ * recon_adjoint / recon_forward on B frames of plan geometry (N, L, M) and
+ * precision prec (the plan's, including RECON_ITER_FP64).  0 on invalid
+ * sizes or precision. */
+size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B, int32_t prec);
 
 /* ---- plan --------------------------------------------------------------- */
 
@@ -179,7 +191,7 @@ recon_status_t recon_gram_apply(recon_plan_t plan, const float* v, int32_t B,
  * stats: optional device recon_stats_t [B].  Requires recon_gram_kernel.
  * lambda >= 0, delta > 0 (ignored for the quadratic penalty), iters >= 0. */
 recon_status_t recon_solve(recon_plan_t plan, const float* y, int32_t B,
-                           float lambda, float delta, int32_t iters,
+                           double lambda, double delta, int32_t iters,
                            int32_t phi, float* x, int32_t x_in_is_x0,
                            void* ws, size_t ws_bytes, recon_stats_t* stats,
                            void* stream);
@@ -194,8 +206,8 @@ recon_status_t recon_solve(recon_plan_t plan, const float* y, int32_t B,
  * (device complex64 [B][N][N]): 0 = x, 1 = r (= Q x - b), 2 = g (gradient),
  * 3 = d (search direction for the next iteration), 4 = b. */
 recon_status_t recon_solve_begin(recon_plan_t plan, const float* y,
-                                 const float* b_in, int32_t B, float lambda,
-                                 float delta, int32_t phi, const float* x0,
+                                 const float* b_in, int32_t B, double lambda,
+                                 double delta, int32_t phi, const float* x0,
                                  void* ws, size_t ws_bytes, void* stream);
 recon_status_t recon_solve_iterate(recon_plan_t plan, int32_t iters, void* ws,
                                    size_t ws_bytes, void* stream);
@@ -237,7 +249,7 @@ recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
 recon_status_t recon_pool_reset(recon_plan_t plan, int32_t B, int32_t phi,
                                 void* ws, size_t ws_bytes, void* stream);
 recon_status_t recon_pool_admit(recon_plan_t plan, int32_t slot, const float* y,
-                                float lambda, float delta, int32_t iters,
+                                double lambda, double delta, int32_t iters,
                                 void* ws, size_t ws_bytes, void* stream);
 recon_status_t recon_pool_step(recon_plan_t plan, int32_t iters, void* ws,
                                size_t ws_bytes, void* stream);

@@ -47,6 +47,18 @@ int default_L(int N) {
   return L;
 }
 
+int base_prec(int32_t prec) { return prec & ~RECON_ITER_FP64; }
+bool iter_f64(int32_t prec) { return (prec & RECON_ITER_FP64) != 0; }
+
+// A plan / workspace precision: one of the NUDFT precisions, optionally with
+// the FP64 iteration (FP64 adjoint only, L <= 1024).
+bool valid_prec(int32_t prec, int32_t L) {
+  const int b = base_prec(prec);
+  if (b < RECON_FP32 || b > RECON_FP64) return false;
+  if (iter_f64(prec) && (b != RECON_FP64 || L > 1024)) return false;
+  return true;
+}
+
 recon_status_t check_geometry(int64_t M, int32_t N, int32_t L) {
   if (N < 2 || N > 1024) return fail(RECON_E_RANGE, "N must be in [2, 1024]");
   if (!is_pow2(L) || L < 64 || L > 2048)
@@ -57,11 +69,12 @@ recon_status_t check_geometry(int64_t M, int32_t N, int32_t L) {
 }
 
 struct PlanLayout {
-  size_t k, ex, ey, tw, khat, at, xs, ph, total;
+  size_t k, ex, ey, tw, khat, at, xs, ph, tw64, khat64, total;
 };
 
-PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
+PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec_full) {
   PlanLayout p{};
+  const int prec = base_prec(prec_full);
   size_t off = 0;
   p.k = off;
   off = align_up(off + (size_t)M * 2 * sizeof(double));
@@ -85,6 +98,13 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec) {
     p.ph = off;
     off = align_up(off + 2 * (size_t)M * phase_record(N) * sizeof(double2));
   }
+  p.tw64 = p.khat64 = 0;
+  if (iter_f64(prec_full)) {  // FP64 twiddles and spectrum of the FP64 iteration
+    p.tw64 = off;
+    off = align_up(off + (size_t)L * sizeof(double2));
+    p.khat64 = off;
+    off = align_up(off + (size_t)L * L * sizeof(double));
+  }
   p.total = off;
   return p;
 }
@@ -94,9 +114,12 @@ struct WsLayout {
   int rows, nb1, nb3, nb4, adj_splits;
 };
 
-WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
+// Images and the row-transform intermediate hold complex64 values, or
+// complex128 with the FP64 iteration (f64).
+WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64) {
   WsLayout w{};
-  const size_t img = (size_t)B * N * N * sizeof(float2);
+  const size_t es = f64 ? sizeof(double2) : sizeof(float2);
+  const size_t img = (size_t)B * N * N * es;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -110,10 +133,10 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B) {
   w.d[0] = take(img);
   w.d[1] = take(img);
   w.qd = take(img);
-  w.T = take((size_t)B * N * L * sizeof(float2));
+  w.T = take((size_t)B * N * L * es);
   w.rows = fft_rows_per_block(L);  // rows per block of every per-row kernel
   w.nb1 = cdiv(N, w.rows);
-  w.nb3 = L / fft_cols_per_block(L);  // <d, Qd> partials come from the column pass
+  w.nb3 = L / fft_cols_per_block(L, f64);  // <d, Qd> partials come from the column pass
   w.nb4 = cdiv(N, w.rows);
   w.p1 = take((size_t)B * w.nb1 * 2 * sizeof(double));
   w.p3 = take((size_t)B * w.nb3 * sizeof(double));
@@ -198,7 +221,8 @@ struct SolveCtx {
 
 struct recon_plan_s {
   int64_t M;
-  int32_t N, L, prec;
+  int32_t N, L, prec;  // prec: NUDFT precision (without RECON_ITER_FP64)
+  bool f64 = false;    // FP64 iteration
   char* mem;
   size_t mem_bytes;
   PlanLayout lay;
@@ -214,6 +238,9 @@ struct recon_plan_s {
   void* at() const { return mem + lay.at; }
   void* xs() const { return mem + lay.xs; }
   double2* ph() const { return reinterpret_cast<double2*>(mem + lay.ph); }
+  double2* tw64() const { return reinterpret_cast<double2*>(mem + lay.tw64); }
+  double* khat64() const { return reinterpret_cast<double*>(mem + lay.khat64); }
+  int32_t prec_full() const { return prec | (f64 ? RECON_ITER_FP64 : 0); }
   bool split() const { return prec == RECON_BF16X3 || prec == RECON_FP16X3; }
   int table_prec() const { return prec; }
   bool has_tables() const { return split(); }
@@ -225,6 +252,9 @@ struct Ws {
   WsLayout lay;
   char* base;
   float2* img(size_t off) const { return reinterpret_cast<float2*>(base + off); }
+  double2* img64(size_t off) const { return reinterpret_cast<double2*>(base + off); }
+  template <typename C>
+  C* at(size_t off) const { return reinterpret_cast<C*>(base + off); }
   double* dbl(size_t off) const { return reinterpret_cast<double*>(base + off); }
   FrameParam* params() const { return reinterpret_cast<FrameParam*>(base + lay.params); }
 };
@@ -232,7 +262,7 @@ struct Ws {
 recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws* out) {
   if (!ws) return fail(RECON_E_ARG, "workspace is NULL");
   if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
-  out->lay = ws_layout(p->M, p->N, p->L, B);
+  out->lay = ws_layout(p->M, p->N, p->L, B, p->f64);
   if (ws_bytes < out->lay.total)
     return fail(RECON_E_NOMEM, "workspace smaller than recon_workspace_bytes");
   out->base = static_cast<char*>(ws);
@@ -256,6 +286,23 @@ recon_status_t gram_apply(recon_plan_t p, const float2* v, float2* out, int B, f
   return RECON_OK;
 }
 
+// The same in FP64 (the FP64 iteration's warm start).
+recon_status_t gram_apply64(recon_plan_t p, const double2* v, double2* out, int B, double2* T,
+                            hipStream_t s) {
+  HIP_TRY(launch_rowfft_plain(p->L, p->N, B, v, T, p->tw64(), s));
+  HIP_TRY(launch_colpass(p->L, p->N, B, T, p->khat64(), nullptr, p->tw64(), nullptr, 0, s));
+  HIP_TRY(launch_rowifft(p->L, p->N, B, T, out, p->tw64(), nullptr, 0, s));
+  return RECON_OK;
+}
+
+// b = A^H y kept in FP64 for the FP64 iteration (FP64 adjoint only).
+recon_status_t adjoint_traced64(recon_plan_t p, const float2* y, int B, double2* b, void* part,
+                                hipStream_t s) {
+  TraceScope ts(TK_ADJ, s);
+  HIP_TRY(launch_adjoint_f64(p->M, p->N, B, p->ph(), y, b, static_cast<double2*>(part), s));
+  return RECON_OK;
+}
+
 recon_status_t adjoint_traced(recon_plan_t p, const float2* y, int B, float2* b, void* part,
                               float* sc, hipStream_t s) {
   TraceScope ts(TK_ADJ, s);
@@ -276,7 +323,7 @@ extern "C" {
 size_t recon_plan_bytes(int64_t M, int32_t N, int32_t L, int32_t prec) {
   if (L == 0) L = default_L(N);
   if (check_geometry(M, N, L) != RECON_OK) return 0;
-  if (prec < 0 || prec > 3) return 0;
+  if (!valid_prec(prec, L)) return 0;
   return plan_layout(M, N, L, prec).total;
 }
 
@@ -286,10 +333,11 @@ size_t recon_gram_workspace_bytes(int64_t M, int32_t N, int32_t L) {
   return gram_ws_layout(M, N, L).total;
 }
 
-size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B) {
+size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B, int32_t prec) {
   if (L == 0) L = default_L(N);
   if (check_geometry(M, N, L) != RECON_OK || B < 1) return 0;
-  return ws_layout(M, N, L, B).total;
+  if (!valid_prec(prec, L)) return 0;
+  return ws_layout(M, N, L, B, iter_f64(prec)).total;
 }
 
 recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, int32_t prec,
@@ -300,7 +348,8 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   if (L == 0) L = default_L(N);
   recon_status_t st = check_geometry(M, N, L);
   if (st != RECON_OK) return st;
-  if (prec < RECON_FP32 || prec > RECON_FP64) return fail(RECON_E_ARG, "unknown precision");
+  if (!valid_prec(prec, L))
+    return fail(RECON_E_ARG, "unknown precision (RECON_ITER_FP64 needs RECON_FP64 and L <= 1024)");
   for (int64_t i = 0; i < 2 * M; ++i) {
     const double v = traj[i];
     if (!std::isfinite(v) || std::fabs(v) > 0.5)
@@ -312,7 +361,8 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
   p->M = M;
   p->N = N;
   p->L = L;
-  p->prec = prec;
+  p->prec = base_prec(prec);
+  p->f64 = iter_f64(prec);
   p->mem = static_cast<char*>(plan_mem);
   p->mem_bytes = plan_mem_bytes;
   p->lay = lay;
@@ -322,14 +372,23 @@ recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, i
     const double a = -2.0 * M_PI * (double)i / (double)L;
     tw[i] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
+  std::vector<double2> tw64(p->f64 ? L : 0);
+  for (int i = 0; i < (int)tw64.size(); ++i) {
+    const double a = -2.0 * M_PI * (double)i / (double)L;
+    tw64[i] = make_double2(std::cos(a), std::sin(a));
+  }
   hipError_t e = hipMemcpyAsync(p->k(), traj, (size_t)M * 2 * sizeof(double),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->tw(), tw.data(), (size_t)L * sizeof(float2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && p->f64)
+    e = hipMemcpyAsync(p->tw64(), tw64.data(), (size_t)L * sizeof(double2), hipMemcpyHostToDevice,
+                       s);
   if (e == hipSuccess) e = launch_tables_f32(M, N, p->k(), p->ex(), p->ey(), s);
   if (e == hipSuccess && p->has_tables())
     e = launch_tables_split(p->table_prec(), M, N, p->k(), p->at(), p->xs(), s);
-  if (e == hipSuccess && prec == RECON_FP64) e = launch_phase_tables_f64(M, N, p->k(), p->ph(), s);
+  if (e == hipSuccess && p->prec == RECON_FP64)
+    e = launch_phase_tables_f64(M, N, p->k(), p->ph(), s);
   // The host copies above read caller and local memory: finish before return.
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -345,7 +404,7 @@ recon_status_t recon_plan_info(recon_plan_t p, int64_t* M, int32_t* N, int32_t* 
   if (M) *M = p->M;
   if (N) *N = p->N;
   if (L) *L = p->L;
-  if (prec) *prec = p->prec;
+  if (prec) *prec = p->prec_full();
   return RECON_OK;
 }
 
@@ -367,7 +426,8 @@ recon_status_t recon_gram_kernel(recon_plan_t p, void* ws, size_t ws_bytes, floa
     HIP_TRY(launch_gram_f64(p->M, p->N, p->k(), part, g.splits, s));
   }
   HIP_TRY(launch_gram_assemble(p->N, p->L, part, g.splits, lag_out, emb, s));
-  HIP_TRY(launch_spectrum_f64(p->L, emb, emb2, p->khat(), khat_out, s));
+  HIP_TRY(launch_spectrum_f64(p->L, emb, emb2, p->khat(), khat_out,
+                              p->f64 ? p->khat64() : nullptr, s));
   p->gram_done = true;
   return RECON_OK;
 }
@@ -419,44 +479,68 @@ recon_status_t recon_gram_apply(recon_plan_t p, const float* v, int32_t B, float
 }
 
 recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
-                                 float lambda, float delta, int32_t phi, const float* x0, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 double lambda, double delta, int32_t phi, const float* x0,
+                                 void* ws, size_t ws_bytes, void* stream) {
   g_last_error.clear();
   if (!p) return fail(RECON_E_ARG, "NULL plan");
   if (!y && !b_in) return fail(RECON_E_ARG, "need y or b");
   if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
   if (phi < 0 || phi > 2) return fail(RECON_E_ARG, "unknown penalty");
-  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
-  if (phi != RECON_PHI_QUADRATIC && (!(delta > 0.f) || !std::isfinite(delta)))
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
+  if (phi != RECON_PHI_QUADRATIC && (!(delta > 0.0) || !std::isfinite(delta)))
     return fail(RECON_E_RANGE, "delta must be > 0");
   Ws w;
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const int N = p->N;
-  float2* b = w.img(w.lay.b);
+  const size_t n_img = (size_t)B * N * N;
   double* yy = w.dbl(w.lay.yy);
   if (y) {
     const float2* y2 = reinterpret_cast<const float2*>(y);
     HIP_TRY(launch_sumsq(p->M, B, y2, w.dbl(w.lay.yyp), yy, s));
-    recon_status_t r = adjoint_traced(p, y2, B, b, w.img(w.lay.adj),
-                                      reinterpret_cast<float*>(w.base + w.lay.sc), s);
+    recon_status_t r =
+        p->f64 ? adjoint_traced64(p, y2, B, w.img64(w.lay.b), w.img(w.lay.adj), s)
+               : adjoint_traced(p, y2, B, w.img(w.lay.b), w.img(w.lay.adj),
+                                reinterpret_cast<float*>(w.base + w.lay.sc), s);
     if (r != RECON_OK) return r;
   } else {
-    HIP_TRY(hipMemcpyAsync(b, b_in, (size_t)B * N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    const float2* b2 = reinterpret_cast<const float2*>(b_in);
+    if (p->f64)
+      HIP_TRY(launch_widen(n_img, b2, w.img64(w.lay.b), s));
+    else
+      HIP_TRY(hipMemcpyAsync(w.img(w.lay.b), b2, n_img * sizeof(float2), hipMemcpyDeviceToDevice,
+                             s));
     HIP_TRY(launch_zero_f64((size_t)B, yy, s));
   }
   HIP_TRY(launch_set_params(B, lambda, delta, INT32_MAX, w.params(), s));
-  const float2* qx0 = nullptr;
-  if (x0) {
-    recon_status_t r = gram_apply(p, reinterpret_cast<const float2*>(x0), w.img(w.lay.qd), B,
-                                  w.img(w.lay.T), nullptr, s);
-    if (r != RECON_OK) return r;
-    qx0 = w.img(w.lay.qd);
+  if (p->f64) {
+    // x0 widened into the second iterate buffer (free before iteration 1)
+    const double2* x0w = nullptr;
+    const double2* qx0 = nullptr;
+    if (x0) {
+      HIP_TRY(launch_widen(n_img, reinterpret_cast<const float2*>(x0), w.img64(w.lay.x[1]), s));
+      x0w = w.img64(w.lay.x[1]);
+      recon_status_t r = gram_apply64(p, x0w, w.img64(w.lay.qd), B, w.img64(w.lay.T), s);
+      if (r != RECON_OK) return r;
+      qx0 = w.img64(w.lay.qd);
+    }
+    HIP_TRY(launch_init(phi, N, w.lay.rows, B, w.img64(w.lay.b), x0w, qx0, w.img64(w.lay.x[0]),
+                        w.img64(w.lay.r), w.img64(w.lay.d[0]), w.dbl(w.lay.p4),
+                        w.dbl(w.lay.pg0), w.params(), s));
+  } else {
+    const float2* qx0 = nullptr;
+    if (x0) {
+      recon_status_t r = gram_apply(p, reinterpret_cast<const float2*>(x0), w.img(w.lay.qd), B,
+                                    w.img(w.lay.T), nullptr, s);
+      if (r != RECON_OK) return r;
+      qx0 = w.img(w.lay.qd);
+    }
+    HIP_TRY(launch_init(phi, N, w.lay.rows, B, w.img(w.lay.b),
+                        reinterpret_cast<const float2*>(x0), qx0, w.img(w.lay.x[0]),
+                        w.img(w.lay.r), w.img(w.lay.d[0]), w.dbl(w.lay.p4), w.dbl(w.lay.pg0),
+                        w.params(), s));
   }
-  HIP_TRY(launch_init(phi, N, w.lay.rows, B, b, reinterpret_cast<const float2*>(x0), qx0,
-                      w.img(w.lay.x[0]), w.img(w.lay.r), w.img(w.lay.d[0]), w.dbl(w.lay.p4),
-                      w.dbl(w.lay.pg0), w.params(), s));
   std::lock_guard<std::mutex> lk(p->mu);
   SolveCtx& c = p->solves[ws];
   c = SolveCtx{};
@@ -475,34 +559,58 @@ static recon_status_t get_ctx(recon_plan_t p, void* ws, SolveCtx* out) {
   return RECON_OK;
 }
 
+}  // extern "C"
+
 // Iterations k0 .. k0+iters-1 of the pseudo-conjugate gradient on every frame
 // of the workspace (frames with stop_at <= k are skipped by the kernels).
-static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
-                                     int iters, hipStream_t s) {
+// C: float2 (FP32 iteration, plan twiddles/spectrum in FP32) or double2.
+template <typename C, typename K>
+static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
+                                       int iters, const C* tw, const K* khat, hipStream_t s) {
   const int N = p->N, L = p->L, B = c.B;
-  float2* T = w.img(w.lay.T);
+  C* T = w.at<C>(w.lay.T);
+  C* r = w.at<C>(w.lay.r);
   for (int it = 0; it < iters; ++it) {
     const int k = k0 + it;
-    float2* d_old = w.img(w.lay.d[k & 1]);
-    float2* d_new = w.img(w.lay.d[(k + 1) & 1]);
-    float2* x_old = w.img(w.lay.x[k & 1]);
-    float2* x_new = w.img(w.lay.x[(k + 1) & 1]);
+    C* d_old = w.at<C>(w.lay.d[k & 1]);
+    C* d_new = w.at<C>(w.lay.d[(k + 1) & 1]);
+    C* x_old = w.at<C>(w.lay.x[k & 1]);
+    C* x_new = w.at<C>(w.lay.x[(k + 1) & 1]);
     {
       TraceScope ts(TK_DIR, s);
-      HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, w.img(w.lay.r), d_old, d_new, x_old, T,
-                                w.dbl(w.lay.p4), w.lay.nb4, w.dbl(w.lay.p1), w.params(), p->tw(),
-                                k, s));
+      HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, r, d_old, d_new, x_old, T, w.dbl(w.lay.p4),
+                                w.lay.nb4, w.dbl(w.lay.p1), w.params(), tw, k, s));
     }
     {
       TraceScope ts(TK_COL, s);
-      HIP_TRY(launch_colpass(L, N, B, T, p->khat(), w.dbl(w.lay.p3), p->tw(), w.params(), k, s));
+      HIP_TRY(launch_colpass(L, N, B, T, khat, w.dbl(w.lay.p3), tw, w.params(), k, s));
     }
     {
       TraceScope ts(TK_UPDATE, s);
-      HIP_TRY(launch_update(L, c.phi, N, B, T, x_old, x_new, d_new, w.img(w.lay.r),
-                            w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3,
-                            w.dbl(w.lay.p4), w.params(), p->tw(), k, s));
+      HIP_TRY(launch_update(L, c.phi, N, B, T, x_old, x_new, d_new, r, w.dbl(w.lay.p1),
+                            w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3, w.dbl(w.lay.p4), w.params(),
+                            tw, k, s));
     }
+  }
+  return RECON_OK;
+}
+
+extern "C" {
+
+static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
+                                     int iters, hipStream_t s) {
+  if (p->f64) return run_iterations_t(p, c, w, k0, iters, p->tw64(), p->khat64(), s);
+  return run_iterations_t(p, c, w, k0, iters, p->tw(), p->khat(), s);
+}
+
+// Copy (FP32 iteration) or round (FP64 iteration) n complex values of the
+// workspace at `off` to the complex64 buffer out.
+static recon_status_t copy_out(recon_plan_t p, const Ws& w, size_t off, size_t n, float2* out,
+                               hipStream_t s) {
+  if (p->f64) {
+    HIP_TRY(launch_narrow(n, w.img64(off), out, s));
+  } else if (out != w.img(off)) {
+    HIP_TRY(hipMemcpyAsync(out, w.img(off), n * sizeof(float2), hipMemcpyDeviceToDevice, s));
   }
   return RECON_OK;
 }
@@ -538,23 +646,48 @@ recon_status_t recon_solve_export(recon_plan_t p, int32_t field, float* out, voi
   st = check_ws(p, ws, ws_bytes, c.B, &w);
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
-  const size_t bytes = (size_t)c.B * p->N * p->N * sizeof(float2);
+  const size_t n = (size_t)c.B * p->N * p->N;
   const int k = c.iters;
   float2* o = reinterpret_cast<float2*>(out);
   switch (field) {
-    case 0: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.x[k & 1]), bytes, hipMemcpyDeviceToDevice, s)); break;
-    case 1: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.r), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 0: return copy_out(p, w, w.lay.x[k & 1], n, o, s);
+    case 1: return copy_out(p, w, w.lay.r, n, o, s);
     case 2:
-      HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img(w.lay.x[k & 1]), w.img(w.lay.r),
-                            nullptr, w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, 0, s));
-      break;
-    case 3:
-      HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img(w.lay.x[k & 1]), w.img(w.lay.r),
-                            w.img(w.lay.d[k & 1]), w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, 1, s));
-      break;
-    case 4: HIP_TRY(hipMemcpyAsync(o, w.img(w.lay.b), bytes, hipMemcpyDeviceToDevice, s)); break;
+    case 3: {
+      const int dir = field == 3;
+      if (p->f64)
+        HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img64(w.lay.x[k & 1]),
+                              w.img64(w.lay.r), dir ? w.img64(w.lay.d[k & 1]) : nullptr,
+                              w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, dir, s));
+      else
+        HIP_TRY(launch_export(c.phi, p->N, w.lay.rows, c.B, w.img(w.lay.x[k & 1]),
+                              w.img(w.lay.r), dir ? w.img(w.lay.d[k & 1]) : nullptr,
+                              w.dbl(w.lay.p4), w.lay.nb4, w.params(), o, dir, s));
+      return RECON_OK;
+    }
+    case 4: return copy_out(p, w, w.lay.b, n, o, s);
     default: return fail(RECON_E_ARG, "unknown field");
   }
+}
+
+// Objective partials and stats of B frames starting at frame f0 of the
+// workspace, whose current iterate sits in x buffer xi.
+static recon_status_t stats_of(recon_plan_t p, const SolveCtx& c, const Ws& w, int f0, int B,
+                               int xi, int iters, recon_stats_t* stats, hipStream_t s) {
+  const int N = p->N;
+  const size_t fo = (size_t)f0 * N * N;
+  double* pobj = w.dbl(w.lay.pobj) + (size_t)f0 * w.lay.nb4 * 3;
+  if (p->f64)
+    HIP_TRY(launch_objective(c.phi, N, w.lay.rows, B, w.img64(w.lay.x[xi]) + fo,
+                             w.img64(w.lay.b) + fo, w.img64(w.lay.r) + fo, pobj,
+                             w.params() + f0, s));
+  else
+    HIP_TRY(launch_objective(c.phi, N, w.lay.rows, B, w.img(w.lay.x[xi]) + fo,
+                             w.img(w.lay.b) + fo, w.img(w.lay.r) + fo, pobj, w.params() + f0,
+                             s));
+  HIP_TRY(launch_stats(B, pobj, w.lay.nb4, w.dbl(w.lay.p4) + (size_t)f0 * w.lay.nb4 * 4,
+                       w.lay.nb4, w.dbl(w.lay.pg0) + (size_t)f0 * w.lay.nb4, w.lay.nb4,
+                       w.dbl(w.lay.yy) + f0, iters, w.params() + f0, stats, s));
   return RECON_OK;
 }
 
@@ -571,21 +704,17 @@ recon_status_t recon_solve_end(recon_plan_t p, float* x_out, recon_stats_t* stat
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const int k = c.iters;
-  float2* x = w.img(w.lay.x[k & 1]);
   if (stats) {
-    HIP_TRY(launch_objective(c.phi, p->N, w.lay.rows, c.B, x, w.img(w.lay.b), w.img(w.lay.r),
-                             w.dbl(w.lay.pobj),
-                             w.params(), s));
-    HIP_TRY(launch_stats(c.B, w.dbl(w.lay.pobj), w.lay.nb4, w.dbl(w.lay.p4), w.lay.nb4,
-                         w.dbl(w.lay.pg0), w.lay.nb4, w.dbl(w.lay.yy), k, w.params(), stats, s));
+    st = stats_of(p, c, w, 0, c.B, k & 1, k, stats, s);
+    if (st != RECON_OK) return st;
   }
-  if (x_out && reinterpret_cast<float2*>(x_out) != x)
-    HIP_TRY(hipMemcpyAsync(x_out, x, (size_t)c.B * p->N * p->N * sizeof(float2),
-                           hipMemcpyDeviceToDevice, s));
+  if (x_out)
+    return copy_out(p, w, w.lay.x[k & 1], (size_t)c.B * p->N * p->N,
+                    reinterpret_cast<float2*>(x_out), s);
   return RECON_OK;
 }
 
-recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, float lambda, float delta,
+recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, double lambda, double delta,
                            int32_t iters, int32_t phi, float* x, int32_t x_in_is_x0, void* ws,
                            size_t ws_bytes, recon_stats_t* stats, void* stream) {
   if (!p || !y || !x) return fail(RECON_E_ARG, "NULL argument");
@@ -610,7 +739,7 @@ recon_status_t recon_pool_reset(recon_plan_t p, int32_t B, int32_t phi, void* ws
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
   if (st != RECON_OK) return st;
   // every slot idle: stop_at = 0
-  HIP_TRY(launch_set_params(B, 0.f, 1.f, 0, w.params(), as_stream(stream)));
+  HIP_TRY(launch_set_params(B, 0.0, 1.0, 0, w.params(), as_stream(stream)));
   std::lock_guard<std::mutex> lk(p->mu);
   SolveCtx& c = p->solves[ws];
   c = SolveCtx{};
@@ -630,8 +759,8 @@ static recon_status_t get_pool(recon_plan_t p, void* ws, SolveCtx* out) {
   return RECON_OK;
 }
 
-recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, float lambda,
-                                float delta, int32_t iters, void* ws, size_t ws_bytes,
+recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, double lambda,
+                                double delta, int32_t iters, void* ws, size_t ws_bytes,
                                 void* stream) {
   g_last_error.clear();
   if (!p || !y) return fail(RECON_E_ARG, "NULL argument");
@@ -641,8 +770,8 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, fl
   if (slot < 0 || slot >= c.B) return fail(RECON_E_RANGE, "slot out of range");
   if (c.stop_at[slot] > c.iters) return fail(RECON_E_STATE, "slot is busy");
   if (iters < 0 || (int64_t)c.iters + iters > INT32_MAX) return fail(RECON_E_RANGE, "bad iteration count");
-  if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
-  if (c.phi != RECON_PHI_QUADRATIC && (!(delta > 0.f) || !std::isfinite(delta)))
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
+  if (c.phi != RECON_PHI_QUADRATIC && (!(delta > 0.0) || !std::isfinite(delta)))
     return fail(RECON_E_RANGE, "delta must be > 0");
   Ws w;
   st = check_ws(p, ws, ws_bytes, c.B, &w);
@@ -654,14 +783,22 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, fl
   const float2* y2 = reinterpret_cast<const float2*>(y);
   HIP_TRY(launch_sumsq(p->M, 1, y2, w.dbl(w.lay.yyp) + (size_t)slot * sumsq_parts(),
                        w.dbl(w.lay.yy) + slot, s));
-  st = adjoint_traced(p, y2, 1, w.img(w.lay.b) + fo, w.img(w.lay.adj),
-                      reinterpret_cast<float*>(w.base + w.lay.sc) + slot, s);
+  st = p->f64 ? adjoint_traced64(p, y2, 1, w.img64(w.lay.b) + fo, w.img(w.lay.adj), s)
+              : adjoint_traced(p, y2, 1, w.img(w.lay.b) + fo, w.img(w.lay.adj),
+                               reinterpret_cast<float*>(w.base + w.lay.sc) + slot, s);
   if (st != RECON_OK) return st;
   const int stop = k + iters;
   HIP_TRY(launch_set_params(1, lambda, delta, stop, w.params() + slot, s));
-  HIP_TRY(launch_init(c.phi, N, w.lay.rows, 1, w.img(w.lay.b) + fo, nullptr, nullptr,
-                      w.img(w.lay.x[k & 1]) + fo, w.img(w.lay.r) + fo, w.img(w.lay.d[k & 1]) + fo, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
-                      w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.params() + slot, s));
+  double* p4 = w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4;
+  double* pg0 = w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4;
+  if (p->f64)
+    HIP_TRY(launch_init(c.phi, N, w.lay.rows, 1, w.img64(w.lay.b) + fo, nullptr, nullptr,
+                        w.img64(w.lay.x[k & 1]) + fo, w.img64(w.lay.r) + fo,
+                        w.img64(w.lay.d[k & 1]) + fo, p4, pg0, w.params() + slot, s));
+  else
+    HIP_TRY(launch_init(c.phi, N, w.lay.rows, 1, w.img(w.lay.b) + fo, nullptr, nullptr,
+                        w.img(w.lay.x[k & 1]) + fo, w.img(w.lay.r) + fo,
+                        w.img(w.lay.d[k & 1]) + fo, p4, pg0, w.params() + slot, s));
   std::lock_guard<std::mutex> lk(p->mu);
   p->solves[ws].start_at[slot] = k;
   p->solves[ws].stop_at[slot] = stop;
@@ -703,18 +840,14 @@ recon_status_t recon_pool_retire(recon_plan_t p, int32_t slot, float* x_out, rec
   hipStream_t s = as_stream(stream);
   const int N = p->N;
   const size_t fo = (size_t)slot * N * N;
-  float2* x = w.img(w.lay.x[stop & 1]) + fo;
   if (stats) {
-    double* pobj = w.dbl(w.lay.pobj) + (size_t)slot * w.lay.nb4 * 3;
-    HIP_TRY(launch_objective(c.phi, N, w.lay.rows, 1, x, w.img(w.lay.b) + fo, w.img(w.lay.r) + fo,
-                             pobj,
-                             w.params() + slot, s));
-    HIP_TRY(launch_stats(1, pobj, w.lay.nb4, w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4,
-                         w.lay.nb4, w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4, w.lay.nb4,
-                         w.dbl(w.lay.yy) + slot, stop - c.start_at[slot], w.params() + slot,
-                         stats, s));
+    st = stats_of(p, c, w, slot, 1, stop & 1, stop - c.start_at[slot], stats, s);
+    if (st != RECON_OK) return st;
   }
-  if (x_out) HIP_TRY(hipMemcpyAsync(x_out, x, (size_t)N * N * sizeof(float2), hipMemcpyDeviceToDevice, s));
+  if (x_out) {
+    const size_t off = w.lay.x[stop & 1] + fo * (p->f64 ? sizeof(double2) : sizeof(float2));
+    return copy_out(p, w, off, (size_t)N * N, reinterpret_cast<float2*>(x_out), s);
+  }
   return RECON_OK;
 }
 

@@ -24,28 +24,40 @@ __global__ void k_zero_f64(size_t n, double* p) {
     p[i] = 0.0;
 }
 
-__global__ void k_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp) {
+__global__ void k_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f < B) fp[f] = FrameParam{lam, delta, stop_at, 0};
 }
 
-template <int PHI>
+// Complex values widened to the FP64 iteration, or rounded back to FP32.
+template <typename O, typename I>
+__global__ void k_convert(size_t n, const I* __restrict__ in, O* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const I v = in[i];
+    out[i] = cmk<O>((real_t<O>)v.x, (real_t<O>)v.y);
+  }
+}
+
+template <int PHI, typename C>
 __global__ __launch_bounds__(256) void k_init(
-    int N, int ROWS, const float2* __restrict__ b, const float2* __restrict__ x0,
-    const float2* __restrict__ qx0, float2* __restrict__ x, float2* __restrict__ r,
-    float2* __restrict__ d, double* __restrict__ p4,
+    int N, int ROWS, const C* __restrict__ b, const C* __restrict__ x0,
+    const C* __restrict__ qx0, C* __restrict__ x, C* __restrict__ r,
+    C* __restrict__ d, double* __restrict__ p4,
     double* __restrict__ pg0, const FrameParam* __restrict__ fp) {
-  extern __shared__ float2 xt[];
+  using R = real_t<C>;
+  extern __shared__ __align__(16) unsigned char init_lds[];
+  C* xt = reinterpret_cast<C*>(init_lds);
   __shared__ double red[1 * 4];
   const int f = blockIdx.y;
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
-  const FrameParam prm = fp[f];
+  const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
   const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);
   for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
     const int rr = i / N, m = i - rr * N;
     const size_t idx = fo + (size_t)(r_lo + rr) * N + m;
-    xt[(r_lo + rr - (n0 - 1)) * N + m] = x0 ? x0[idx] : make_float2(0.f, 0.f);
+    xt[(r_lo + rr - (n0 - 1)) * N + m] = x0 ? x0[idx] : cmk<C>(0, 0);
   }
   __syncthreads();
   double acc[1] = {0.0};
@@ -54,17 +66,17 @@ __global__ __launch_bounds__(256) void k_init(
     const int rr = i / N, m = i - rr * N;
     const int n = n0 + rr;
     const size_t idx = fo + (size_t)n * N + m;
-    const float2* mid = xt + (rr + 1) * N;
-    const float2* up = (n > 0) ? mid - N : nullptr;
-    const float2* dn = (n + 1 < N) ? mid + N : nullptr;
-    const float2 div = divergence<PHI>(up, mid, dn, m, N, prm.delta);
-    const float2 bv = b[idx];
-    const float2 q = qx0 ? qx0[idx] : make_float2(0.f, 0.f);
-    const float2 rn = c_sub(q, bv);
-    const float2 gn = make_float2(fmaf(prm.lam, div.x, 2.f * rn.x), fmaf(prm.lam, div.y, 2.f * rn.y));
+    const C* mid = xt + (rr + 1) * N;
+    const C* up = (n > 0) ? mid - N : nullptr;
+    const C* dn = (n + 1 < N) ? mid + N : nullptr;
+    const C div = divergence<PHI>(up, mid, dn, m, N, delta);
+    const C bv = b[idx];
+    const C q = qx0 ? qx0[idx] : cmk<C>(0, 0);
+    const C rn = c_sub(q, bv);
+    const C gn = cmk<C>(rfma(lam, div.x, 2 * rn.x), rfma(lam, div.y, 2 * rn.y));
     x[idx] = mid[m];
     r[idx] = rn;
-    d[idx] = make_float2(0.f, 0.f);
+    d[idx] = cmk<C>(0, 0);
     acc[0] += (double)gn.x * (double)gn.x + (double)gn.y * (double)gn.y;
   }
   block_sum<1>(acc, red);
@@ -82,10 +94,10 @@ __global__ __launch_bounds__(256) void k_init(
 // Criterion J = ||y||^2 - 2 Re<x, b> + Re<x, Qx> + lam sum phi(|Dx|)
 // (Section 3.4, Eq. NewCritLS) with Qx = r + b:
 // partials [Re<x, b>, Re<x, r>, sum phi] per block.
-template <int PHI>
-__global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const float2* __restrict__ x,
-                                                   const float2* __restrict__ b,
-                                                   const float2* __restrict__ r,
+template <int PHI, typename C>
+__global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const C* __restrict__ x,
+                                                   const C* __restrict__ b,
+                                                   const C* __restrict__ r,
                                                    double* __restrict__ pobj,
                                                    const FrameParam* __restrict__ fp) {
   __shared__ double red[3 * 4];
@@ -99,16 +111,16 @@ __global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const float2
     const int rr = i / N, m = i - rr * N;
     const int n = n0 + rr;
     const size_t idx = fo + (size_t)n * N + m;
-    const float2 xv = x[idx], bv = b[idx], rv = r[idx];
+    const C xv = x[idx], bv = b[idx], rv = r[idx];
     acc[0] += (double)xv.x * bv.x + (double)xv.y * bv.y;
     acc[1] += (double)xv.x * rv.x + (double)xv.y * rv.y;
     if (n + 1 < N) {
-      const float2 xd = x[idx + N];
+      const C xd = x[idx + N];
       const double tx = (double)xd.x - xv.x, ty = (double)xd.y - xv.y;
       acc[2] += pen_phi<PHI>(tx * tx + ty * ty, delta);
     }
     if (m + 1 < N) {
-      const float2 xr = x[idx + 1];
+      const C xr = x[idx + 1];
       const double tx = (double)xr.x - xv.x, ty = (double)xr.y - xv.y;
       acc[2] += pen_phi<PHI>(tx * tx + ty * ty, delta);
     }
@@ -155,19 +167,21 @@ __global__ void k_stats(int B, const double* __restrict__ pobj, int nbo,
 // The gradient g = 2 r + lam D^T(w(Dx) Dx) of the current iterate, or the
 // pending direction -g + beta d_old (as the next direction kernel forms
 // it), into out.  Rows n0-1 .. n0+ROWS of x are staged in LDS.
-template <int PHI>
-__global__ __launch_bounds__(256) void k_export(int N, int ROWS, const float2* __restrict__ x,
-                                                const float2* __restrict__ r,
-                                                const float2* __restrict__ d_old,
+template <int PHI, typename C>
+__global__ __launch_bounds__(256) void k_export(int N, int ROWS, const C* __restrict__ x,
+                                                const C* __restrict__ r,
+                                                const C* __restrict__ d_old,
                                                 const double* __restrict__ p4, int nb4,
                                                 const FrameParam* __restrict__ fp,
                                                 float2* __restrict__ out, int dir) {
-  extern __shared__ float2 xt[];
+  using R = real_t<C>;
+  extern __shared__ __align__(16) unsigned char exp_lds[];
+  C* xt = reinterpret_cast<C*>(exp_lds);
   const int f = blockIdx.y;
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
-  const FrameParam prm = fp[f];
-  float bf = 0.f;
+  const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
+  R bf = 0;
   if (dir) {
     const double* pf = p4 + (size_t)f * nb4 * 4;
     const double gg = wave_sum_partials(pf + 0, nb4, 4);
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(256) void k_export(int N, int ROWS, const float2* _
     double beta = 0.0;
     if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
     if (-gg + beta * gdo >= 0.0) beta = 0.0;
-    bf = (float)beta;
+    bf = (R)beta;
   }
   const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);
   for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
@@ -190,16 +204,16 @@ __global__ __launch_bounds__(256) void k_export(int N, int ROWS, const float2* _
     const int rr = i / N, m = i - rr * N;
     const int n = n0 + rr;
     const size_t idx = fo + (size_t)n * N + m;
-    const float2* mid = xt + (rr + 1) * N;
-    const float2 div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
-                                       n + 1 < N ? mid + N : nullptr, m, N, prm.delta);
-    const float2 rv = r[idx];
-    const float2 g = make_float2(fmaf(prm.lam, div.x, 2.f * rv.x), fmaf(prm.lam, div.y, 2.f * rv.y));
+    const C* mid = xt + (rr + 1) * N;
+    const C div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                  n + 1 < N ? mid + N : nullptr, m, N, delta);
+    const C rv = r[idx];
+    const C g = cmk<C>(rfma(lam, div.x, 2 * rv.x), rfma(lam, div.y, 2 * rv.y));
     if (dir) {
-      const float2 dv = d_old[idx];
-      out[idx] = make_float2(fmaf(bf, dv.x, -g.x), fmaf(bf, dv.y, -g.y));
+      const C dv = d_old[idx];
+      out[idx] = to_f32(cmk<C>(rfma(bf, dv.x, -g.x), rfma(bf, dv.y, -g.y)));
     } else {
-      out[idx] = g;
+      out[idx] = to_f32(g);
     }
   }
 }
@@ -218,28 +232,49 @@ hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp,
+hipError_t launch_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp,
                              hipStream_t s) {
   k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, stop_at, fp);
   return hipGetLastError();
 }
 
+template <typename C>
+static hipError_t init_any(int phi, int N, int R, int B, const C* b, const C* x0, const C* qx0,
+                           C* x, C* r, C* d, double* p4, double* pg0, const FrameParam* fp,
+                           hipStream_t s) {
+  dim3 grid(cdiv(N, R), B);
+  const size_t shm = (size_t)(R + 2) * N * sizeof(C);
+  RECON_PHI_SWITCH(phi, (k_init<PP, C><<<grid, 256, shm, s>>>(N, R, b, x0, qx0, x, r, d, p4,
+                                                              pg0, fp)));
+  return hipGetLastError();
+}
 hipError_t launch_init(int phi, int N, int R, int B, const float2* b, const float2* x0,
                        const float2* qx0, float2* x, float2* r, float2* d,
                        double* p4, double* pg0, const FrameParam* fp, hipStream_t s) {
-  dim3 grid(cdiv(N, R), B);
-  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
-  RECON_PHI_SWITCH(phi, (k_init<PP><<<grid, 256, shm, s>>>(N, R, b, x0, qx0, x, r, d, p4,
-                                                           pg0, fp)));
-  return hipGetLastError();
+  return init_any(phi, N, R, B, b, x0, qx0, x, r, d, p4, pg0, fp, s);
+}
+hipError_t launch_init(int phi, int N, int R, int B, const double2* b, const double2* x0,
+                       const double2* qx0, double2* x, double2* r, double2* d,
+                       double* p4, double* pg0, const FrameParam* fp, hipStream_t s) {
+  return init_any(phi, N, R, B, b, x0, qx0, x, r, d, p4, pg0, fp, s);
 }
 
+template <typename C>
+static hipError_t objective_any(int phi, int N, int R, int B, const C* x, const C* b, const C* r,
+                                double* pobj, const FrameParam* fp, hipStream_t s) {
+  dim3 grid(cdiv(N, R), B);
+  RECON_PHI_SWITCH(phi, (k_objective<PP, C><<<grid, 256, 0, s>>>(N, R, x, b, r, pobj, fp)));
+  return hipGetLastError();
+}
 hipError_t launch_objective(int phi, int N, int R, int B, const float2* x, const float2* b,
                             const float2* r, double* pobj, const FrameParam* fp,
                             hipStream_t s) {
-  dim3 grid(cdiv(N, R), B);
-  RECON_PHI_SWITCH(phi, (k_objective<PP><<<grid, 256, 0, s>>>(N, R, x, b, r, pobj, fp)));
-  return hipGetLastError();
+  return objective_any(phi, N, R, B, x, b, r, pobj, fp, s);
+}
+hipError_t launch_objective(int phi, int N, int R, int B, const double2* x, const double2* b,
+                            const double2* r, double* pobj, const FrameParam* fp,
+                            hipStream_t s) {
+  return objective_any(phi, N, R, B, x, b, r, pobj, fp, s);
 }
 
 hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4, int nb4,
@@ -250,14 +285,40 @@ hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4, in
   return hipGetLastError();
 }
 
+template <typename C>
+static hipError_t export_any(int phi, int N, int R, int B, const C* x, const C* r,
+                             const C* d_old, const double* p4, int nb4, const FrameParam* fp,
+                             float2* out, int dir, hipStream_t s) {
+  dim3 grid(cdiv(N, R), B);
+  const size_t shm = (size_t)(R + 2) * N * sizeof(C);
+  RECON_PHI_SWITCH(phi, (k_export<PP, C><<<grid, 256, shm, s>>>(N, R, x, r, d_old, p4, nb4, fp,
+                                                                out, dir)));
+  return hipGetLastError();
+}
 hipError_t launch_export(int phi, int N, int R, int B, const float2* x, const float2* r,
                          const float2* d_old, const double* p4, int nb4, const FrameParam* fp,
                          float2* out, int dir, hipStream_t s) {
-  dim3 grid(cdiv(N, R), B);
-  const size_t shm = (size_t)(R + 2) * N * sizeof(float2);
-  RECON_PHI_SWITCH(phi, (k_export<PP><<<grid, 256, shm, s>>>(N, R, x, r, d_old, p4, nb4, fp, out,
-                                                             dir)));
+  return export_any(phi, N, R, B, x, r, d_old, p4, nb4, fp, out, dir, s);
+}
+hipError_t launch_export(int phi, int N, int R, int B, const double2* x, const double2* r,
+                         const double2* d_old, const double* p4, int nb4, const FrameParam* fp,
+                         float2* out, int dir, hipStream_t s) {
+  return export_any(phi, N, R, B, x, r, d_old, p4, nb4, fp, out, dir, s);
+}
+
+template <typename O, typename I>
+static hipError_t convert_any(size_t n, const I* in, O* out, hipStream_t s) {
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks == 0) return hipSuccess;
+  k_convert<O, I><<<(unsigned)blocks, 256, 0, s>>>(n, in, out);
   return hipGetLastError();
+}
+hipError_t launch_widen(size_t n, const float2* in, double2* out, hipStream_t s) {
+  return convert_any(n, in, out, s);
+}
+hipError_t launch_narrow(size_t n, const double2* in, float2* out, hipStream_t s) {
+  return convert_any(n, in, out, s);
 }
 
 }  // namespace recon

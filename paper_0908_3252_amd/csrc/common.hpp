@@ -25,6 +25,40 @@ __device__ __forceinline__ float2 c_cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float c_abs2(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
+// The same operations on FP64 complex values (the FP64 iteration).
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double c_abs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+
+// Real type of an interleaved complex type, construction and fused
+// multiply-add for either precision of the iteration.
+template <typename C> struct CxTraits;
+template <> struct CxTraits<float2> { using R = float; };
+template <> struct CxTraits<double2> { using R = double; };
+template <typename C> using real_t = typename CxTraits<C>::R;
+
+template <typename C>
+__device__ __forceinline__ C cmk(real_t<C> re, real_t<C> im) {
+  if constexpr (sizeof(C) == 8) return make_float2(re, im);
+  else return make_double2(re, im);
+}
+__device__ __forceinline__ float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return fma(a, b, c); }
+// a * s + c for complex a, c and real s.
+template <typename C>
+__device__ __forceinline__ C c_axpy(real_t<C> s, C a, C c) {
+  return cmk<C>(rfma(s, a.x, c.x), rfma(s, a.y, c.y));
+}
+// Complex value rounded to FP32 / widened from FP32.
+__device__ __forceinline__ float2 to_f32(float2 a) { return a; }
+__device__ __forceinline__ float2 to_f32(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <typename C>
+__device__ __forceinline__ C from_f32(float2 a) { return cmk<C>(a.x, a.y); }
+
 // Sum over the 64 lanes of a wavefront in a fixed tree order (xor
 // butterflies), so the result is identical on every lane and every run.
 __device__ __forceinline__ double wave_sum(double v) {

@@ -44,47 +44,49 @@ struct FftShape {
 // write pattern of the first passes across banks.
 __device__ __forceinline__ int lpad(int p) { return p + (p >> 3); }
 
-template <bool INV>
-__device__ __forceinline__ float2 mul_w4(float2 a) {  // a * exp(-+ 2 pi i / 4)
-  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+// The transforms are written once for both element types: C = float2 (the
+// FP32 iteration and the plain Gram apply) or double2 (the FP64 iteration).
+template <bool INV, typename C>
+__device__ __forceinline__ C mul_w4(C a) {  // a * exp(-+ 2 pi i / 4)
+  return INV ? cmk<C>(-a.y, a.x) : cmk<C>(a.y, -a.x);
 }
-template <bool INV>
-__device__ __forceinline__ float2 mul_w8(float2 a) {  // a * exp(-+ 2 pi i / 8)
-  const float s = 0.70710678118654752440f;
-  return INV ? make_float2((a.x - a.y) * s, (a.x + a.y) * s)
-             : make_float2((a.x + a.y) * s, (a.y - a.x) * s);
+template <bool INV, typename C>
+__device__ __forceinline__ C mul_w8(C a) {  // a * exp(-+ 2 pi i / 8)
+  const real_t<C> s = (real_t<C>)0.70710678118654752440;
+  return INV ? cmk<C>((a.x - a.y) * s, (a.x + a.y) * s)
+             : cmk<C>((a.x + a.y) * s, (a.y - a.x) * s);
 }
-template <bool INV>
-__device__ __forceinline__ float2 mul_w8_3(float2 a) {  // a * exp(-+ 2 pi i 3 / 8)
-  const float s = 0.70710678118654752440f;
-  return INV ? make_float2((-a.x - a.y) * s, (a.x - a.y) * s)
-             : make_float2((a.y - a.x) * s, (-a.x - a.y) * s);
+template <bool INV, typename C>
+__device__ __forceinline__ C mul_w8_3(C a) {  // a * exp(-+ 2 pi i 3 / 8)
+  const real_t<C> s = (real_t<C>)0.70710678118654752440;
+  return INV ? cmk<C>((-a.x - a.y) * s, (a.x - a.y) * s)
+             : cmk<C>((a.y - a.x) * s, (-a.x - a.y) * s);
 }
 
 // In-place R-point DFTs, natural order in and out.  HALF: a[R/2..R-1] = 0.
-template <bool INV, bool HALF>
-__device__ __forceinline__ void dft2(float2* a) {
+template <bool INV, bool HALF, typename C>
+__device__ __forceinline__ void dft2(C* a) {
   if (HALF) {
     a[1] = a[0];
   } else {
-    const float2 t = a[0];
+    const C t = a[0];
     a[0] = c_add(t, a[1]);
     a[1] = c_sub(t, a[1]);
   }
 }
 
-template <bool INV, bool HALF>
-__device__ __forceinline__ void dft4(float2* a) {
+template <bool INV, bool HALF, typename C>
+__device__ __forceinline__ void dft4(C* a) {
   if (HALF) {
-    const float2 w = mul_w4<INV>(a[1]);
-    const float2 a0 = a[0], a1 = a[1];
+    const C w = mul_w4<INV>(a[1]);
+    const C a0 = a[0], a1 = a[1];
     a[0] = c_add(a0, a1);
     a[2] = c_sub(a0, a1);
     a[1] = c_add(a0, w);
     a[3] = c_sub(a0, w);
   } else {
-    const float2 s02 = c_add(a[0], a[2]), d02 = c_sub(a[0], a[2]);
-    const float2 s13 = c_add(a[1], a[3]), d13 = mul_w4<INV>(c_sub(a[1], a[3]));
+    const C s02 = c_add(a[0], a[2]), d02 = c_sub(a[0], a[2]);
+    const C s13 = c_add(a[1], a[3]), d13 = mul_w4<INV>(c_sub(a[1], a[3]));
     a[0] = c_add(s02, s13);
     a[2] = c_sub(s02, s13);
     a[1] = c_add(d02, d13);
@@ -92,10 +94,10 @@ __device__ __forceinline__ void dft4(float2* a) {
   }
 }
 
-template <bool INV, bool HALF>
-__device__ __forceinline__ void dft8(float2* a) {
-  float2 e[4] = {a[0], a[2], a[4], a[6]};
-  float2 o[4] = {a[1], a[3], a[5], a[7]};
+template <bool INV, bool HALF, typename C>
+__device__ __forceinline__ void dft8(C* a) {
+  C e[4] = {a[0], a[2], a[4], a[6]};
+  C o[4] = {a[1], a[3], a[5], a[7]};
   dft4<INV, HALF>(e);
   dft4<INV, HALF>(o);
   o[1] = mul_w8<INV>(o[1]);
@@ -108,24 +110,23 @@ __device__ __forceinline__ void dft8(float2* a) {
   }
 }
 
-template <int R, bool INV, bool HALF>
-__device__ __forceinline__ void dft(float2* a) {
+template <int R, bool INV, bool HALF, typename C>
+__device__ __forceinline__ void dft(C* a) {
   if constexpr (R == 2) dft2<INV, HALF>(a);
   else if constexpr (R == 4) dft4<INV, HALF>(a);
   else dft8<INV, HALF>(a);
 }
 
 // One Stockham pass; returns the output positions of v[e] in pos[e].
-template <int L, int R, int NS, bool INV, bool HALF>
-__device__ __forceinline__ void fft_pass(float2 (&v)[8], int t, const float2* tw,
-                                         int (&pos)[8]) {
+template <int L, int R, int NS, bool INV, bool HALF, typename C>
+__device__ __forceinline__ void fft_pass(C (&v)[8], int t, const C* tw, int (&pos)[8]) {
   constexpr int NB = 8 / R;
   constexpr int T = L / 8;
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int j = t + u * T;
     const int k = j & (NS - 1);
-    float2 a[R];
+    C a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
     if constexpr (NS > 1) {
@@ -134,7 +135,7 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[8], int t, const float2* tw
       constexpr int OFF = NS - FftShape<L>::S0;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[OFF + (r - 1) * NS + k];
+        C w = tw[OFF + (r - 1) * NS + k];
         if (INV) w.y = -w.y;
         a[r] = c_mul(a[r], w);
       }
@@ -169,16 +170,15 @@ __device__ __forceinline__ void team_sync() {
   }
 }
 
-template <int L, bool INV, bool HALF_IN, int P, int NS>
-__device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
-                                           float2* buf1, const float2* tw) {
+template <int L, bool INV, bool HALF_IN, int P, int NS, typename C>
+__device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* buf0, C* buf1, const C* tw) {
   using S = FftShape<L>;
   constexpr int R = (P == 0 && S::REM) ? (1 << S::REM) : 8;
   constexpr bool HALF = HALF_IN && (P == 0);
   int pos[8];
   fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
   if constexpr (P + 1 < S::NP) {
-    float2* buf = (FftSync<L>::WAVE_LOCAL || !(P & 1)) ? buf0 : buf1;
+    C* buf = (FftSync<L>::WAVE_LOCAL || !(P & 1)) ? buf0 : buf1;
 #pragma unroll
     for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
     team_sync<L>();
@@ -196,12 +196,11 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[8], int t, float2* buf0,
 // buf0/buf1: this team's LDS buffers of PAD entries (buf1 unused when the
 // team is wave-local; it may then alias buf0); tw: the per-pass LDS twiddle
 // table built by load_twiddles.
-template <int L, bool INV, bool HALF_IN>
-__device__ __forceinline__ void fft_team(float2 (&v)[8], int t, float2* buf0,
-                                         float2* buf1, const float2* tw) {
+template <int L, bool INV, bool HALF_IN, typename C>
+__device__ __forceinline__ void fft_team(C (&v)[8], int t, C* buf0, C* buf1, const C* tw) {
   if (HALF_IN) {
 #pragma unroll
-    for (int e = 4; e < 8; ++e) v[e] = make_float2(0.f, 0.f);
+    for (int e = 4; e < 8; ++e) v[e] = cmk<C>(0, 0);
   }
   fft_passes<L, INV, HALF_IN, 0, 1>(v, t, buf0, buf1, tw);
 }
@@ -215,8 +214,8 @@ constexpr int fft_team_lds() {
 // Build the per-pass twiddle table in LDS (TWN <= L entries) from the plan's
 // table g[i] = exp(-2 pi i i / L): entry NS - S0 + (r - 1) NS + k of the pass
 // of span NS holds g[r k L / (8 NS)].
-template <int L>
-__device__ __forceinline__ void load_twiddles(float2* tw, const float2* __restrict__ g) {
+template <int L, typename C>
+__device__ __forceinline__ void load_twiddles(C* tw, const C* __restrict__ g) {
   using S = FftShape<L>;
   for (int i = threadIdx.x; i < S::TWN; i += blockDim.x) {
     int ns = S::S0;

@@ -49,19 +49,21 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& f) {
 }
 
 // g = 2 r + lam * div, as every kernel forms it.
-__device__ __forceinline__ float2 grad_from(float2 r, float2 div, float lam) {
-  return make_float2(fmaf(lam, div.x, 2.f * r.x), fmaf(lam, div.y, 2.f * r.y));
+template <typename C>
+__device__ __forceinline__ C grad_from(C r, C div, real_t<C> lam) {
+  return cmk<C>(rfma(lam, div.x, 2 * r.x), rfma(lam, div.y, 2 * r.y));
 }
 
 // ------------------------------------------------------- direction + rows
-template <int L, int PHI>
+template <int L, int PHI, typename C>
 __global__ __launch_bounds__(256) void k_dir_rowfft(
-    int N, const float2* __restrict__ r, const float2* __restrict__ d_old,
-    float2* __restrict__ d_new, const float2* __restrict__ x, float2* __restrict__ T,
-    const double* __restrict__ p4, int nb4, double* __restrict__ p1,
-    const FrameParam* __restrict__ fp, const float2* __restrict__ twg, int kit) {
-  using C = RowCfg<L>;
-  constexpr int TT = C::TT, ROWS = C::ROWS, W = C::W, EPT = C::EPT;
+    int N, const C* __restrict__ r, const C* __restrict__ d_old, C* __restrict__ d_new,
+    const C* __restrict__ x, C* __restrict__ T, const double* __restrict__ p4, int nb4,
+    double* __restrict__ p1, const FrameParam* __restrict__ fp, const C* __restrict__ twg,
+    int kit) {
+  using RC = RowCfg<L>;
+  using R = real_t<C>;
+  constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
   constexpr int XT = (ROWS + 3) * W;      // x rows n0-1 .. n0+ROWS+1
   constexpr int DT = (ROWS + 1) * W;      // d rows n0 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L>();
@@ -72,20 +74,20 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
-  __shared__ float2 tw[L];
-  __shared__ float2 sh[SH];
+  __shared__ C tw[L];
+  __shared__ C sh[SH];
   __shared__ double red[2 * 4];
-  __shared__ float sbeta;
-  float2* Xt = sh;       // tile row i <-> image row n0 - 1 + i (stride N)
-  float2* Dt = sh + XT;  // tile row i <-> image row n0 + i
+  __shared__ R sbeta;
+  C* Xt = sh;       // tile row i <-> image row n0 - 1 + i (stride N)
+  C* Dt = sh + XT;  // tile row i <-> image row n0 + i
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
   const int n = n0 + team;
-  const float2 zero = make_float2(0.f, 0.f);
+  const C zero = cmk<C>(0, 0);
 
   // -- loads: own pixels, then the halo rows
-  float2 xo[EPT], ro[EPT], dv[EPT];
+  C xo[EPT], ro[EPT], dv[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     ro[e] = r[idx];
     dv[e] = d_old[idx];
   }
-  float2 hx[HX], hr[HD], hd[HD];
+  C hx[HX], hr[HD], hd[HD];
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
@@ -125,9 +127,9 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     double beta = 0.0;
     if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
     if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
-    if (threadIdx.x == 0) sbeta = (float)beta;
+    if (threadIdx.x == 0) sbeta = (R)beta;
   }
-  const float lam = fp[f].lam, delta = fp[f].delta;
+  const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
 
   // -- x tile
 #pragma unroll
@@ -143,24 +145,24 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     if (j < 3 * W && m < N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
   }
   __syncthreads();
-  const float bf = sbeta;
+  const R bf = sbeta;
 
   // -- gradient and new direction: own rows and the halo row n0 + ROWS
   double gd = 0.0;
-  float2 dn[EPT];
-  float wdn[EPT], wrt[EPT];
+  C dn[EPT];
+  R wdn[EPT], wrt[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
     dn[e] = zero;
-    wdn[e] = wrt[e] = 0.f;
+    wdn[e] = wrt[e] = 0;
     if (n < N && m < N) {
-      const float2* mid = Xt + (team + 1) * N;
-      const float2 div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
-                                            n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
-                                            wrt[e]);
-      const float2 g = grad_from(ro[e], div, lam);
-      dn[e] = make_float2(fmaf(bf, dv[e].x, -g.x), fmaf(bf, dv[e].y, -g.y));
+      const C* mid = Xt + (team + 1) * N;
+      const C div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                       n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
+                                       wrt[e]);
+      const C g = grad_from(ro[e], div, lam);
+      dn[e] = cmk<C>(rfma(bf, dv[e].x, -g.x), rfma(bf, dv[e].y, -g.y));
       Dt[team * N + m] = dn[e];
       d_new[fo + (size_t)n * N + m] = dn[e];
       gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
@@ -172,11 +174,10 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     for (int s = 0; s < HD; ++s) {
       const int m = threadIdx.x + s * 256;
       if (m < N) {
-        const float2* mid = Xt + (ROWS + 1) * N;
-        const float2 div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N,
-                                           delta);
-        const float2 g = grad_from(hr[s], div, lam);
-        Dt[ROWS * N + m] = make_float2(fmaf(bf, hd[s].x, -g.x), fmaf(bf, hd[s].y, -g.y));
+        const C* mid = Xt + (ROWS + 1) * N;
+        const C div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
+        const C g = grad_from(hr[s], div, lam);
+        Dt[ROWS * N + m] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
       }
     }
   }
@@ -189,13 +190,13 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     const int m = t + e * TT;
     if (n < N && m < N) {
       // the weights of the pixel's forward edges come from the divergence
-      const float2 e0 = Dt[team * N + m];
+      const C e0 = Dt[team * N + m];
       if (n + 1 < N) {
-        const float2 te = c_sub(Dt[(team + 1) * N + m], e0);
+        const C te = c_sub(Dt[(team + 1) * N + m], e0);
         cv += (double)wdn[e] * (double)c_abs2(te);
       }
       if (m + 1 < N) {
-        const float2 te = c_sub(Dt[team * N + m + 1], e0);
+        const C te = c_sub(Dt[team * N + m + 1], e0);
         cv += (double)wrt[e] * (double)c_abs2(te);
       }
     }
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   }
 
   // -- row FFT of d (team layout in = own pixels)
-  float2 val[8];
+  C val[8];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) val[e] = dn[e];
   fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L>(),
@@ -217,22 +218,22 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
                                (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD),
                            tw);
   if (n < N) {
-    float2* out = T + ((size_t)f * N + n) * L;
+    C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
     for (int e = 0; e < 8; ++e) out[t + e * TT] = val[e];
   }
 }
 
 // ------------------------------------------------ inverse rows + update
-template <int L, int PHI>
+template <int L, int PHI, typename C>
 __global__ __launch_bounds__(256) void k_update(
-    int N, const float2* __restrict__ T, const float2* __restrict__ x_old,
-    float2* __restrict__ x_new, const float2* __restrict__ d, float2* __restrict__ r,
-    const double* __restrict__ p1, int nb1, const double* __restrict__ p3, int nb3,
-    double* __restrict__ p4, const FrameParam* __restrict__ fp, const float2* __restrict__ twg,
-    int kit) {
-  using C = RowCfg<L>;
-  constexpr int TT = C::TT, ROWS = C::ROWS, W = C::W, EPT = C::EPT;
+    int N, const C* __restrict__ T, const C* __restrict__ x_old, C* __restrict__ x_new,
+    const C* __restrict__ d, C* __restrict__ r, const double* __restrict__ p1, int nb1,
+    const double* __restrict__ p3, int nb3, double* __restrict__ p4,
+    const FrameParam* __restrict__ fp, const C* __restrict__ twg, int kit) {
+  using RC = RowCfg<L>;
+  using R = real_t<C>;
+  constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
   constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L>();
   constexpr int SH = (2 * XT > FFTB) ? 2 * XT : FFTB;
@@ -240,25 +241,25 @@ __global__ __launch_bounds__(256) void k_update(
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;
-  __shared__ float2 tw[L];
-  __shared__ float2 sh[SH];
+  __shared__ C tw[L];
+  __shared__ C sh[SH];
   __shared__ double red[4 * 4];
-  __shared__ float salpha;
-  float2* Xo = sh;       // x at the start of the iteration; row i <-> image row n0-1+i
-  float2* Xn = sh + XT;  // x + alpha d
+  __shared__ R salpha;
+  C* Xo = sh;       // x at the start of the iteration; row i <-> image row n0-1+i
+  C* Xn = sh + XT;  // x + alpha d
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
   const int n = n0 + team;
 
   // -- loads: the transformed row, own pixels, halo rows
-  float2 val[8];
+  C val[8];
   {
-    const float2* row = T + ((size_t)f * N + (n < N ? n : 0)) * L;
+    const C* row = T + ((size_t)f * N + (n < N ? n : 0)) * L;
 #pragma unroll
     for (int e = 0; e < 8; ++e) val[e] = row[t + e * TT];
   }
-  float2 xo[EPT], dv[EPT], ro[EPT];
+  C xo[EPT], dv[EPT], ro[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void k_update(
     dv[e] = d[idx];
     ro[e] = r[idx];
   }
-  float2 hx[HX], hd[HX];
+  C hx[HX], hd[HX];
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
@@ -282,18 +283,18 @@ __global__ __launch_bounds__(256) void k_update(
 
   // Step length: exact minimiser of the half-quadratic majorant along d
   // (one wavefront reduces, the block reads it after the barrier).
-  const float lam = fp[f].lam, delta = fp[f].delta;
+  const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
   if (threadIdx.x < 64) {
     const double* q1 = p1 + (size_t)f * nb1 * 2;
     const double gd = wave_sum_partials(q1 + 0, nb1, 2);
     const double cvv = wave_sum_partials(q1 + 1, nb1, 2);
     const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
-    const double den = 2.0 * dqd + (double)lam * cvv;
+    const double den = 2.0 * dqd + fp[f].lam * cvv;
     const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
-    if (threadIdx.x == 0) salpha = (float)alpha;
+    if (threadIdx.x == 0) salpha = (R)alpha;
   }
   __syncthreads();  // twiddles, step length
-  const float af = salpha;
+  const R af = salpha;
 
   // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
   fft_team<L, true, false>(val, t, sh + team * fft_team_lds<L>(),
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void k_update(
     const int m = t + e * TT;
     if (n < N && m < N) {
       Xo[(team + 1) * N + m] = xo[e];
-      Xn[(team + 1) * N + m] = make_float2(fmaf(af, dv[e].x, xo[e].x), fmaf(af, dv[e].y, xo[e].y));
+      Xn[(team + 1) * N + m] = c_axpy(af, dv[e], xo[e]);
     }
   }
 #pragma unroll
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(256) void k_update(
     if (j < 2 * W && m < N && img >= 0 && img < N) {
       const int o = (img - n0 + 1) * N + m;
       Xo[o] = hx[s];
-      Xn[o] = make_float2(fmaf(af, hd[s].x, hx[s].x), fmaf(af, hd[s].y, hx[s].y));
+      Xn[o] = c_axpy(af, hd[s], hx[s]);
     }
   }
   __syncthreads();
@@ -329,15 +330,15 @@ __global__ __launch_bounds__(256) void k_update(
     const int m = t + e * TT;
     if (n < N && m < N) {
       const size_t idx = fo + (size_t)n * N + m;
-      const float2* mo = Xo + (team + 1) * N;
-      const float2* mn = Xn + (team + 1) * N;
-      const float2 div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
-                                           n + 1 < N ? mo + N : nullptr, m, N, delta);
-      const float2 div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
-                                           n + 1 < N ? mn + N : nullptr, m, N, delta);
-      const float2 go = grad_from(ro[e], div_o, lam);
-      const float2 rn = make_float2(fmaf(af, val[e].x, ro[e].x), fmaf(af, val[e].y, ro[e].y));
-      const float2 gn = grad_from(rn, div_n, lam);
+      const C* mo = Xo + (team + 1) * N;
+      const C* mn = Xn + (team + 1) * N;
+      const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
+                                      n + 1 < N ? mo + N : nullptr, m, N, delta);
+      const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
+                                      n + 1 < N ? mn + N : nullptr, m, N, delta);
+      const C go = grad_from(ro[e], div_o, lam);
+      const C rn = c_axpy(af, val[e], ro[e]);
+      const C gn = grad_from(rn, div_n, lam);
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
@@ -356,6 +357,7 @@ __global__ __launch_bounds__(256) void k_update(
 }
 
 // ------------------------------------------------------------------ launchers
+// (the FP64 iteration, C = double2, is built for L <= 1024)
 #define RECON_ITER_L_SWITCH(L_, CALL)                    \
   switch (L_) {                                          \
     case 64: { constexpr int LL = 64; CALL; } break;     \
@@ -363,7 +365,12 @@ __global__ __launch_bounds__(256) void k_update(
     case 256: { constexpr int LL = 256; CALL; } break;   \
     case 512: { constexpr int LL = 512; CALL; } break;   \
     case 1024: { constexpr int LL = 1024; CALL; } break; \
-    case 2048: { constexpr int LL = 2048; CALL; } break; \
+    case 2048: {                                         \
+      if constexpr (sizeof(C) == 8) {                    \
+        constexpr int LL = 2048;                         \
+        CALL;                                            \
+      }                                                  \
+    } break;                                             \
     default: return hipErrorInvalidValue;                \
   }
 #define RECON_ITER_PHI_SWITCH(PHI_, CALL)             \
@@ -374,28 +381,57 @@ __global__ __launch_bounds__(256) void k_update(
     default: return hipErrorInvalidValue;             \
   }
 
+template <typename C>
+static hipError_t dir_rowfft_any(int L, int phi, int N, int B, const C* r, const C* d_old,
+                                 C* d_new, const C* x, C* T, const double* p4, int nb4, double* p1,
+                                 const FrameParam* fp, const C* tw, int k, hipStream_t s) {
+  if (N > L / 2) return hipErrorInvalidValue;
+  if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP, C><<<grid, 256, 0, s>>>(
+                                                        N, r, d_old, d_new, x, T, p4, nb4, p1,
+                                                        fp, tw, k))));
+  return hipGetLastError();
+}
+
+template <typename C>
+static hipError_t update_any(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
+                             const C* d, C* r, const double* p1, int nb1, const double* p3,
+                             int nb3, double* p4, const FrameParam* fp, const C* tw, int k,
+                             hipStream_t s) {
+  if (N > L / 2) return hipErrorInvalidValue;
+  if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C><<<grid, 256, 0, s>>>(
+                                                        N, T, x_old, x_new, d, r, p1, nb1, p3,
+                                                        nb3, p4, fp, tw, k))));
+  return hipGetLastError();
+}
+
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
                              const float2* tw, int k, hipStream_t s) {
-  if (N > L / 2) return hipErrorInvalidValue;
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP><<<grid, 256, 0, s>>>(
-                                                        N, r, d_old, d_new, x, T, p4, nb4, p1,
-                                                        fp, tw, k))));
-  return hipGetLastError();
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s);
+}
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
+                             const double2* d_old, double2* d_new, const double2* x, double2* T,
+                             const double* p4, int nb4, double* p1, const FrameParam* fp,
+                             const double2* tw, int k, hipStream_t s) {
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s);
 }
 
 hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
                          const float2* tw, int k, hipStream_t s) {
-  if (N > L / 2) return hipErrorInvalidValue;
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP><<<grid, 256, 0, s>>>(
-                                                        N, T, x_old, x_new, d, r, p1, nb1, p3,
-                                                        nb3, p4, fp, tw, k))));
-  return hipGetLastError();
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, s);
+}
+hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
+                         double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
+                         const double* p3, int nb3, double* p4, const FrameParam* fp,
+                         const double2* tw, int k, hipStream_t s) {
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, s);
 }
 
 }  // namespace recon

@@ -14,32 +14,43 @@ constexpr int RECON_PREC_FP16X3 = 2;
 // part in iteration k of its workspace only while k < stop_at (slot pools of
 // the serving path; plain solves use INT32_MAX).
 struct FrameParam {
-  float lam;
-  float delta;
+  double lam;
+  double delta;
   int32_t stop_at;
   int32_t pad;
 };
 
 // Rows handled by one 256-thread block of the row-FFT kernels.
 inline int fft_rows_per_block(int L) { return 2048 / L; }
-// Columns handled by one block of the column kernel.
-int fft_cols_per_block(int L);
+// Columns handled by one block of the column kernel (f64: the FP64 form).
+int fft_cols_per_block(int L, bool f64);
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Every kernel of the Gram apply and of the iteration exists for float2 (the
+// FP32 iteration) and, for L <= 1024, double2 (the FP64 iteration: state,
+// transforms and spectrum in FP64); the double2 overloads take the plan's
+// FP64 twiddles and spectrum.
 
 // ---- Gram apply (Section 3.4) ------------------------------------------------
 // Row pass: T[f][n][:] = FFT_L(zero-padded v[f][n][:]) for n < N.
 hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
                                const float2* tw, hipStream_t s);
+hipError_t launch_rowfft_plain(int L, int N, int B, const double2* v, double2* T,
+                               const double2* tw, hipStream_t s);
 // Column pass (in place): column q of T[f] -> IFFT_L(khat_s[q][:] * FFT_L(col)),
 // rows n < N kept.  khat_s is the transposed spectrum scaled by 1/L^2.
 // p3 (optional, [B][L / cols_per_block]) receives per-block partials of
 // sum khat_s |FFT_L(col)|^2 = Re<v, Q v> (Parseval).
 hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
                           const float2* tw, const FrameParam* fp, int k, hipStream_t s);
+hipError_t launch_colpass(int L, int N, int B, double2* T, const double* khat_s, double* p3,
+                          const double2* tw, const FrameParam* fp, int k, hipStream_t s);
 // Row inverse pass: out[f][n][m] = IFFT_L(T[f][n][:])[m] for m < N.
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
                           const float2* tw, const FrameParam* fp, int k, hipStream_t s);
+hipError_t launch_rowifft(int L, int N, int B, const double2* T, double2* out,
+                          const double2* tw, const FrameParam* fp, int k, hipStream_t s);
 
 
 // ---- CG kernels (Section 3.3) -------------------------------------------------
@@ -53,6 +64,10 @@ hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
                              const float2* tw, int k, hipStream_t s);
+hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
+                             const double2* d_old, double2* d_new, const double2* x, double2* T,
+                             const double* p4, int nb4, double* p1, const FrameParam* fp,
+                             const double2* tw, int k, hipStream_t s);
 // Row inverse pass of the Gram apply fused with the update: Qd = rows of
 // IFFT(T) cropped; alpha from the partials; x_new = x + alpha d,
 // r += alpha Qd; partials for beta from g_old (recomputed from r, x) and
@@ -61,18 +76,32 @@ hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const fl
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
                          const float2* tw, int k, hipStream_t s);
+hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
+                         double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
+                         const double* p3, int nb3, double* p4, const FrameParam* fp,
+                         const double2* tw, int k, hipStream_t s);
 // Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), d = 0; partials
 // such that the first direction is -g, g = 2r + grad R(x0).  R rows per block.
 hipError_t launch_init(int phi, int N, int R, int B, const float2* b,
                        const float2* x0, const float2* qx0, float2* x,
                        float2* r, float2* d, double* p4,
                        double* pg0, const FrameParam* fp, hipStream_t s);
+hipError_t launch_init(int phi, int N, int R, int B, const double2* b,
+                       const double2* x0, const double2* qx0, double2* x,
+                       double2* r, double2* d, double* p4,
+                       double* pg0, const FrameParam* fp, hipStream_t s);
 hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s);
-hipError_t launch_set_params(int B, float lam, float delta, int stop_at, FrameParam* fp,
+hipError_t launch_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp,
                              hipStream_t s);
+// n complex values widened to FP64 / rounded to FP32.
+hipError_t launch_widen(size_t n, const float2* in, double2* out, hipStream_t s);
+hipError_t launch_narrow(size_t n, const double2* in, float2* out, hipStream_t s);
 // Objective partials and final statistics.
 hipError_t launch_objective(int phi, int N, int R, int B, const float2* x,
                             const float2* b, const float2* r, double* pobj,
+                            const FrameParam* fp, hipStream_t s);
+hipError_t launch_objective(int phi, int N, int R, int B, const double2* x,
+                            const double2* b, const double2* r, double* pobj,
                             const FrameParam* fp, hipStream_t s);
 hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4,
                         int nb4, const double* pg0, int nbg, const double* yy,
@@ -82,6 +111,9 @@ hipError_t launch_stats(int B, const double* pobj, int nbo, const double* p4,
 // as the next direction kernel would form it) of the current iterate.
 hipError_t launch_export(int phi, int N, int R, int B, const float2* x, const float2* r,
                          const float2* d_old, const double* p4, int nb4, const FrameParam* fp,
+                         float2* out, int dir, hipStream_t s);
+hipError_t launch_export(int phi, int N, int R, int B, const double2* x, const double2* r,
+                         const double2* d_old, const double* p4, int nb4, const FrameParam* fp,
                          float2* out, int dir, hipStream_t s);
 
 // ---- NUDFT (Section 2, Appendix A.2) -------------------------------------------
@@ -134,10 +166,10 @@ hipError_t launch_gram_f64(int64_t M, int N, const double* k, double* part,
 hipError_t launch_gram_assemble(int N, int L, const double* part, int splits,
                                 double* lag_out, double2* emb, hipStream_t s);
 // FP64 2D FFT of the embedding (emb is overwritten, tmp is scratch of the
-// same size), then khat_s[q][p] = Re K[p][q] / L^2 (FP32, transposed) and
-// optionally khat_out[p][q] = Re K[p][q].
+// same size), then khat_s[q][p] = Re K[p][q] / L^2 (FP32, transposed),
+// optionally khat_out[p][q] = Re K[p][q] and khat64_s (khat_s in FP64).
 hipError_t launch_spectrum_f64(int L, double2* emb, double2* tmp, float* khat_s,
-                               float* khat_out, hipStream_t s);
+                               float* khat_out, double* khat64_s, hipStream_t s);
 // Adjoint accumulated in FP64 (phasors generated in FP64 from k); b FP32.
 // part: split-K partials, FP64 complex [splits][group][N][N].
 // FP64 phase tables of the accurate adjoint: phase_record(N) double2 per
@@ -146,5 +178,7 @@ int phase_record(int N);
 hipError_t launch_phase_tables_f64(int64_t M, int N, const double* k, double2* ph, hipStream_t s);
 hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
                               float2* b, double2* part, hipStream_t s);
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
+                              double2* b, double2* part, hipStream_t s);
 
 }  // namespace recon

@@ -77,13 +77,15 @@ __device__ __forceinline__ void adj_fetch(int64_t M, int R, const double2* __res
   yv = yf[lc];
 }
 
-// grid: (n-tiles, m-tiles * frames, splits)
+// grid: (n-tiles, m-tiles * frames, splits).  O: float2 (b for the FP32
+// iteration) or double2 (b kept in FP64 for the FP64 iteration).
+template <typename O>
 __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, int splits,
                                                      const double2* __restrict__ ph,
                                                      int R,
                                                      const float2* __restrict__ y,
                                                      double2* __restrict__ part,
-                                                     float2* __restrict__ out, float scale) {
+                                                     O* __restrict__ out, double scale) {
   __shared__ double Ar[AK][ALD], Ai[AK][ALD], Zr[AK][ALD], Zi[AK][ALD];
   const int mt = (N + AT - 1) / AT;
   const int n0 = blockIdx.x * AT;
@@ -177,8 +179,8 @@ __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, in
         if (n < N && m < N) {
           const size_t o = (size_t)n * N + m;
           if (splits == 1) {
-            out[(size_t)f * N * N + o] = make_float2((float)(cr[a][b][r] * scale),
-                                                     (float)(ci[a][b][r] * scale));
+            out[(size_t)f * N * N + o] = cmk<O>((real_t<O>)(cr[a][b][r] * scale),
+                                                (real_t<O>)(ci[a][b][r] * scale));
           } else {
             part[((size_t)s * B + f) * (size_t)N * N + o] = make_double2(cr[a][b][r], ci[a][b][r]);
           }
@@ -186,8 +188,9 @@ __global__ __launch_bounds__(256) void k_adjoint_f64(int64_t M, int N, int B, in
       }
 }
 
+template <typename O>
 __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __restrict__ part,
-                                   float2* __restrict__ b, double scale) {
+                                   O* __restrict__ b, double scale) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x) {
     double2 acc = part[i];
@@ -196,35 +199,46 @@ __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __re
       acc.x += v.x;
       acc.y += v.y;
     }
-    b[i] = make_float2((float)(acc.x * scale), (float)(acc.y * scale));
+    b[i] = cmk<O>((real_t<O>)(acc.x * scale), (real_t<O>)(acc.y * scale));
   }
 }
 
-hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
-                              float2* b, double2* part, hipStream_t s) {
+template <typename O>
+static hipError_t adjoint_f64_any(int64_t M, int N, int B, const double2* ph, const float2* y,
+                                  O* b, double2* part, hipStream_t s) {
   const int sp = adjoint_splits(M, N);
   const int R = phase_record(N);
   if (sp == 1) {
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * B, 1);
-    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, B, 1, ph, R, y, nullptr, b, 1.0f / (float)N);
+    k_adjoint_f64<O><<<grid, 256, 0, s>>>(M, N, B, 1, ph, R, y, nullptr, b, 1.0 / (double)N);
     return hipGetLastError();
   }
   const int G = adjoint_group(M, N);
   for (int f0 = 0; f0 < B; f0 += G) {
     const int g = (B - f0 < G) ? B - f0 : G;
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * g, sp);
-    k_adjoint_f64<<<grid, 256, 0, s>>>(M, N, g, sp, ph, R, y + (size_t)f0 * M, part, nullptr, 1.0f);
+    k_adjoint_f64<O><<<grid, 256, 0, s>>>(M, N, g, sp, ph, R, y + (size_t)f0 * M, part,
+                                          (O*)nullptr, 1.0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t count = (size_t)g * N * N;
     size_t blocks = (count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    k_split_reduce_f64<<<(int)blocks, 256, 0, s>>>(count, sp, part, b + (size_t)f0 * N * N,
-                                                  1.0 / (double)N);
+    k_split_reduce_f64<O><<<(int)blocks, 256, 0, s>>>(count, sp, part, b + (size_t)f0 * N * N,
+                                                     1.0 / (double)N);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
+                              float2* b, double2* part, hipStream_t s) {
+  return adjoint_f64_any(M, N, B, ph, y, b, part, s);
+}
+hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
+                              double2* b, double2* part, hipStream_t s) {
+  return adjoint_f64_any(M, N, B, ph, y, b, part, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,21 +287,24 @@ __global__ void k_transpose_f64(int L, const double2* __restrict__ in, double2* 
   }
 }
 
-// khat_s[q][p] = Re(spec_t[q][p]) / L^2 ; khat_out[p][q] = Re(spec_t[q][p]).
+// khat_s[q][p] = Re(spec_t[q][p]) / L^2 ; khat_out[p][q] = Re(spec_t[q][p]);
+// khat64_s (optional): khat_s without the rounding to FP32.
 __global__ void k_khat_finish_f64(int L, const double2* __restrict__ spec_t,
-                                  float* __restrict__ khat_s, float* __restrict__ khat_out) {
+                                  float* __restrict__ khat_s, float* __restrict__ khat_out,
+                                  double* __restrict__ khat64_s) {
   const double inv = 1.0 / ((double)L * (double)L);
   const int total = L * L;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const int q = i / L, p = i - q * L;
     const double v = spec_t[i].x;
     khat_s[i] = (float)(v * inv);
+    if (khat64_s) khat64_s[i] = v * inv;
     if (khat_out) khat_out[(size_t)p * L + q] = (float)v;
   }
 }
 
 hipError_t launch_spectrum_f64(int L, double2* emb, double2* tmp, float* khat_s, float* khat_out,
-                               hipStream_t s) {
+                               double* khat64_s, hipStream_t s) {
   int logL = 0;
   while ((1 << logL) < L) ++logL;
   const size_t shm = 2 * (size_t)L * sizeof(double2);
@@ -303,7 +320,7 @@ hipError_t launch_spectrum_f64(int L, double2* emb, double2* tmp, float* khat_s,
   if (e != hipSuccess) return e;
   int blocks = cdiv(L * L, 256);
   if (blocks > 65536) blocks = 65536;
-  k_khat_finish_f64<<<blocks, 256, 0, s>>>(L, tmp, khat_s, khat_out);
+  k_khat_finish_f64<<<blocks, 256, 0, s>>>(L, tmp, khat_s, khat_out, khat64_s);
   return hipGetLastError();
 }
 

@@ -22,6 +22,19 @@ __device__ __forceinline__ float pen_weight(float s2, float delta) {
   }
 }
 
+// FP64 weights (the FP64 iteration): correctly rounded square root and
+// division.
+template <int PHI>
+__device__ __forceinline__ double pen_weight(double s2, double delta) {
+  if constexpr (PHI == 0) {
+    return 1.0 / sqrt(fma(delta, delta, s2));
+  } else if constexpr (PHI == 1) {
+    return (s2 <= delta * delta) ? 2.0 : 2.0 * delta / sqrt(s2);
+  } else {
+    return 2.0;
+  }
+}
+
 template <int PHI>
 __device__ __forceinline__ double pen_phi(double s2, double delta) {
   if constexpr (PHI == 0) {
@@ -34,9 +47,9 @@ __device__ __forceinline__ double pen_phi(double s2, double delta) {
 }
 
 // w(|t|) t for the difference t = b - a.
-template <int PHI>
-__device__ __forceinline__ float2 wdiff(float2 a, float2 b, float delta) {
-  const float2 t = c_sub(b, a);
+template <int PHI, typename C>
+__device__ __forceinline__ C wdiff(C a, C b, real_t<C> delta) {
+  const C t = c_sub(b, a);
   return c_scale(t, pen_weight<PHI>(c_abs2(t), delta));
 }
 
@@ -46,23 +59,22 @@ __device__ __forceinline__ float2 wdiff(float2 a, float2 b, float delta) {
 // columns 0..N-2 (non-periodic).  Also returns the weights of the pixel's
 // forward edges (down: (n, m)-(n+1, m), right: (n, m)-(n, m+1); 0 where the
 // edge does not exist), which the curvature of the majorant reuses.
-template <int PHI>
-__device__ __forceinline__ float2 divergence_fw(const float2* up, const float2* mid,
-                                                const float2* dn, int m, int N, float delta,
-                                                float& w_dn, float& w_rt) {
-  const float2 c = mid[m];
-  float2 acc = make_float2(0.f, 0.f);
-  w_dn = 0.f;
-  w_rt = 0.f;
+template <int PHI, typename C>
+__device__ __forceinline__ C divergence_fw(const C* up, const C* mid, const C* dn, int m, int N,
+                                           real_t<C> delta, real_t<C>& w_dn, real_t<C>& w_rt) {
+  const C c = mid[m];
+  C acc = cmk<C>(0, 0);
+  w_dn = 0;
+  w_rt = 0;
   if (up) acc = c_add(acc, wdiff<PHI>(up[m], c, delta));
   if (dn) {
-    const float2 t = c_sub(dn[m], c);
+    const C t = c_sub(dn[m], c);
     w_dn = pen_weight<PHI>(c_abs2(t), delta);
     acc = c_sub(acc, c_scale(t, w_dn));
   }
   if (m > 0) acc = c_add(acc, wdiff<PHI>(mid[m - 1], c, delta));
   if (m + 1 < N) {
-    const float2 t = c_sub(mid[m + 1], c);
+    const C t = c_sub(mid[m + 1], c);
     w_rt = pen_weight<PHI>(c_abs2(t), delta);
     acc = c_sub(acc, c_scale(t, w_rt));
   }
@@ -70,11 +82,10 @@ __device__ __forceinline__ float2 divergence_fw(const float2* up, const float2* 
 }
 
 // The same without the weights (one code path, so the same values).
-template <int PHI>
-__device__ __forceinline__ float2 divergence(const float2* up, const float2* mid,
-                                             const float2* dn, int m, int N,
-                                             float delta) {
-  float w_dn, w_rt;
+template <int PHI, typename C>
+__device__ __forceinline__ C divergence(const C* up, const C* mid, const C* dn, int m, int N,
+                                        real_t<C> delta) {
+  real_t<C> w_dn, w_rt;
   return divergence_fw<PHI>(up, mid, dn, m, N, delta, w_dn, w_rt);
 }
 

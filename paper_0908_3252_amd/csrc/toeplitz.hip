@@ -21,39 +21,39 @@
 namespace recon {
 
 // Exchange buffers of one team inside a block-shared array.
-template <int L>
-__device__ __forceinline__ float2* team_buf0(float2* base, int team) {
+template <int L, typename C>
+__device__ __forceinline__ C* team_buf0(C* base, int team) {
   return base + team * fft_team_lds<L>();
 }
-template <int L>
-__device__ __forceinline__ float2* team_buf1(float2* base, int team) {
+template <int L, typename C>
+__device__ __forceinline__ C* team_buf1(C* base, int team) {
   return team_buf0<L>(base, team) + (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD);
 }
 
 // ----------------------------------------------------------------- row pass
-template <int L>
-__global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __restrict__ v,
-                                                      float2* __restrict__ T,
-                                                      const float2* __restrict__ twg) {
+template <int L, typename C>
+__global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict__ v,
+                                                      C* __restrict__ T,
+                                                      const C* __restrict__ twg) {
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
-  __shared__ float2 tw[L];
-  __shared__ float2 bufs[ROWS * fft_team_lds<L>()];
+  __shared__ C tw[L];
+  __shared__ C bufs[ROWS * fft_team_lds<L>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
   load_twiddles<L>(tw, twg);
-  float2 val[8];
-  const float2* row = v + ((size_t)f * N + n) * N;
+  C val[8];
+  const C* row = v + ((size_t)f * N + n) * N;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int p = t + e * S::T;
-    val[e] = (n < N && p < N) ? row[p] : make_float2(0.f, 0.f);
+    val[e] = (n < N && p < N) ? row[p] : cmk<C>(0, 0);
   }
   __syncthreads();
   fft_team<L, false, true>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
   if (n < N) {
-    float2* out = T + ((size_t)f * N + n) * L;
+    C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
     for (int e = 0; e < 8; ++e) out[t + e * S::T] = val[e];
   }
@@ -63,46 +63,45 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const float2* __res
 // Block = COLS columns of frame f, THREADS threads (TEAMS = THREADS / (L/8)
 // columns transformed at once).  With p3 != NULL the block also writes the
 // partial sum over its columns of khat_s |FFT(pad col)|^2, which by Parseval
-// is its share of Re<v, Q v>.
-template <int L>
+// is its share of Re<v, Q v>.  FP64 elements (ES = 2) halve the columns per
+// block (and the threads at L = 512) so that the tile stays within LDS.
+template <int L, int ES = 1>
 struct ColCfg {
   static constexpr int T = L / 8;
-  static constexpr int THREADS = (L == 512) ? 512 : 256;
+  static constexpr int THREADS = (L == 512 && ES == 1) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
-  static constexpr int COLS = (L <= 64) ? 32 : (L <= 512 ? 16 : 8);
+  static constexpr int COLS = ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
   static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
 };
 
-template <int L>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* __restrict__ T,
-                                                               const float* __restrict__ khat_s,
-                                                               double* __restrict__ p3,
-                                                               const float2* __restrict__ twg,
-                                                               const FrameParam* __restrict__ fp,
-                                                               int kit) {
+template <int L, typename C>
+__global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass(
+    int N, C* __restrict__ T, const real_t<C>* __restrict__ khat_s, double* __restrict__ p3,
+    const C* __restrict__ twg, const FrameParam* __restrict__ fp, int kit) {
   using S = FftShape<L>;
-  using C = ColCfg<L>;
+  using CC = ColCfg<L, sizeof(C) / 8>;
+  using R = real_t<C>;
   if (fp && kit >= fp[blockIdx.y].stop_at) return;
-  constexpr int COLS = C::COLS;
-  constexpr int TEAMS = C::TEAMS;
-  constexpr int NT = C::THREADS;
+  constexpr int COLS = CC::COLS;
+  constexpr int TEAMS = CC::TEAMS;
+  constexpr int NT = CC::THREADS;
   // Column-major tile: column c at tile[c * TS + n].  TS = L/2 + 4 makes the
   // column stride 8 words mod 64 banks, so both the row-wise global staging
   // (consecutive threads -> consecutive columns) and the column-wise FFT
   // gathers (consecutive threads -> consecutive rows) are conflict-free.
   constexpr int TS = L / 2 + 4;
-  __shared__ float2 tw[L];
-  __shared__ float2 tile[COLS * TS];
-  __shared__ float2 bufs[TEAMS * fft_team_lds<L>()];
+  __shared__ C tw[L];
+  __shared__ C tile[COLS * TS];
+  __shared__ C bufs[TEAMS * fft_team_lds<L>()];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
   const int q0 = blockIdx.x * COLS;
-  float2* Tf = T + (size_t)f * N * L;
+  C* Tf = T + (size_t)f * N * L;
   double dqd = 0.0;
   // Stage the block's columns: every load of a thread is issued before the
   // first LDS store (static count: N <= L/2).
   constexpr int SMAX = (L / 2) * COLS / NT;
-  float2 stg[SMAX];
+  C stg[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) {
     const int i = threadIdx.x + s * NT;
@@ -118,27 +117,27 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* _
   }
   __syncthreads();
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
-  float2* b0 = team_buf0<L>(bufs, team);
-  float2* b1 = team_buf1<L>(bufs, team);
+  C* b0 = team_buf0<L>(bufs, team);
+  C* b1 = team_buf1<L>(bufs, team);
   // Wave-local teams touch only their own columns and buffers: no block
   // barrier inside the loop.  Multi-wave teams synchronise inside the FFT.
 #pragma unroll 1
   for (int c0 = 0; c0 < COLS; c0 += TEAMS) {
     const int c = c0 + team;
     const bool active = c < COLS;  // uniform per team
-    float2 val[8];
+    C val[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int p = t + e * S::T;
-      val[e] = (active && p < N) ? tile[c * TS + p] : make_float2(0.f, 0.f);
+      val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
     fft_team<L, false, true>(val, t, b0, b1, tw);
-    const float* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
-    float acc = 0.f;
+    const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
+    R acc = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const float kv = kq[t + e * S::T];
-      acc = fmaf(kv, c_abs2(val[e]), acc);
+      const R kv = kq[t + e * S::T];
+      acc = rfma(kv, c_abs2(val[e]), acc);
       val[e] = c_scale(val[e], kv);
     }
     if (active) dqd += (double)acc;
@@ -168,24 +167,23 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_colpass(int N, float2* _
 }
 
 // --------------------------------------------------------- row inverse pass
-template <int L>
-__global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict__ T,
-                                                 float2* __restrict__ out,
-                                                 const float2* __restrict__ twg,
+template <int L, typename C>
+__global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
+                                                 C* __restrict__ out, const C* __restrict__ twg,
                                                  const FrameParam* __restrict__ fp, int kit) {
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   if (fp && kit >= fp[blockIdx.y].stop_at) return;
-  __shared__ float2 tw[L];
-  __shared__ float2 bufs[ROWS * fft_team_lds<L>()];
+  __shared__ C tw[L];
+  __shared__ C bufs[ROWS * fft_team_lds<L>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
   load_twiddles<L>(tw, twg);
-  float2 val[8];
-  const float2* row = T + ((size_t)f * N + n) * L;
+  C val[8];
+  const C* row = T + ((size_t)f * N + n) * L;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : make_float2(0.f, 0.f);
+  for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : cmk<C>(0, 0);
   __syncthreads();
   fft_team<L, true, false>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
   if (n < N) {
@@ -199,6 +197,7 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict
 }
 
 // ------------------------------------------------------------------ launchers
+// (the FP64 forms, C = double2, are built for L <= 1024)
 #define RECON_L_SWITCH(L_, CALL)                         \
   switch (L_) {                                          \
     case 64: { constexpr int LL = 64; CALL; } break;     \
@@ -206,42 +205,80 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const float2* __restrict
     case 256: { constexpr int LL = 256; CALL; } break;   \
     case 512: { constexpr int LL = 512; CALL; } break;   \
     case 1024: { constexpr int LL = 1024; CALL; } break; \
-    case 2048: { constexpr int LL = 2048; CALL; } break; \
+    case 2048: {                                         \
+      if constexpr (sizeof(C) == 8) {                    \
+        constexpr int LL = 2048;                         \
+        CALL;                                            \
+      }                                                  \
+    } break;                                             \
     default: return hipErrorInvalidValue;                \
   }
 
-int fft_cols_per_block(int L) {
+int fft_cols_per_block(int L, bool f64) {
   switch (L) {
-    case 64: return ColCfg<64>::COLS;
-    case 128: return ColCfg<128>::COLS;
-    case 256: return ColCfg<256>::COLS;
-    case 512: return ColCfg<512>::COLS;
-    case 1024: return ColCfg<1024>::COLS;
+    case 64: return f64 ? ColCfg<64, 2>::COLS : ColCfg<64>::COLS;
+    case 128: return f64 ? ColCfg<128, 2>::COLS : ColCfg<128>::COLS;
+    case 256: return f64 ? ColCfg<256, 2>::COLS : ColCfg<256>::COLS;
+    case 512: return f64 ? ColCfg<512, 2>::COLS : ColCfg<512>::COLS;
+    case 1024: return f64 ? ColCfg<1024, 2>::COLS : ColCfg<1024>::COLS;
     case 2048: return ColCfg<2048>::COLS;
     default: return 1;
   }
 }
 
+template <typename C>
+static hipError_t rowfft_plain_any(int L, int N, int B, const C* v, C* T, const C* tw,
+                                   hipStream_t s) {
+  if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_L_SWITCH(L, (k_rowfft_plain<LL, C><<<grid, 256, 0, s>>>(N, v, T, tw)));
+  return hipGetLastError();
+}
+
+template <typename C>
+static hipError_t colpass_any(int L, int N, int B, C* T, const real_t<C>* khat_s, double* p3,
+                              const C* tw, const FrameParam* fp, int k, hipStream_t s) {
+  if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  dim3 grid(L / fft_cols_per_block(L, sizeof(C) == 16), B);
+  RECON_L_SWITCH(L, (k_colpass<LL, C><<<grid, ColCfg<LL, sizeof(C) / 8>::THREADS, 0, s>>>(
+                        N, T, khat_s, p3, tw, fp, k)));
+  return hipGetLastError();
+}
+
+template <typename C>
+static hipError_t rowifft_any(int L, int N, int B, const C* T, C* out, const C* tw,
+                              const FrameParam* fp, int k, hipStream_t s) {
+  if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_L_SWITCH(L, (k_rowifft<LL, C><<<grid, 256, 0, s>>>(N, T, out, tw, fp, k)));
+  return hipGetLastError();
+}
+
 hipError_t launch_rowfft_plain(int L, int N, int B, const float2* v, float2* T,
                                const float2* tw, hipStream_t s) {
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_L_SWITCH(L, (k_rowfft_plain<LL><<<grid, 256, 0, s>>>(N, v, T, tw)));
-  return hipGetLastError();
+  return rowfft_plain_any(L, N, B, v, T, tw, s);
+}
+hipError_t launch_rowfft_plain(int L, int N, int B, const double2* v, double2* T,
+                               const double2* tw, hipStream_t s) {
+  return rowfft_plain_any(L, N, B, v, T, tw, s);
 }
 
 hipError_t launch_colpass(int L, int N, int B, float2* T, const float* khat_s, double* p3,
                           const float2* tw, const FrameParam* fp, int k, hipStream_t s) {
-  dim3 grid(L / fft_cols_per_block(L), B);
-  RECON_L_SWITCH(L, (k_colpass<LL><<<grid, ColCfg<LL>::THREADS, 0, s>>>(N, T, khat_s, p3, tw, fp,
-                                                                        k)));
-  return hipGetLastError();
+  return colpass_any(L, N, B, T, khat_s, p3, tw, fp, k, s);
+}
+hipError_t launch_colpass(int L, int N, int B, double2* T, const double* khat_s, double* p3,
+                          const double2* tw, const FrameParam* fp, int k, hipStream_t s) {
+  return colpass_any(L, N, B, T, khat_s, p3, tw, fp, k, s);
 }
 
 hipError_t launch_rowifft(int L, int N, int B, const float2* T, float2* out,
                           const float2* tw, const FrameParam* fp, int k, hipStream_t s) {
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_L_SWITCH(L, (k_rowifft<LL><<<grid, 256, 0, s>>>(N, T, out, tw, fp, k)));
-  return hipGetLastError();
+  return rowifft_any(L, N, B, T, out, tw, fp, k, s);
+}
+hipError_t launch_rowifft(int L, int N, int B, const double2* T, double2* out,
+                          const double2* tw, const FrameParam* fp, int k, hipStream_t s) {
+  return rowifft_any(L, N, B, T, out, tw, fp, k, s);
 }
 
 }  // namespace recon

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(HERE, "librecon.so")
 
 OK, E_ARG, E_RANGE, E_NOMEM, E_HIP, E_STATE, E_NONFINITE = range(7)
 FP32, BF16X3, FP16X3, FP64 = 0, 1, 2, 3
+# Flag OR'ed into FP64: the iteration itself in FP64 (state, FFTs, spectrum).
+ITER_FP64 = 16
+FP64_ITER64 = FP64 | ITER_FP64
 PHI = {"hyperbolic": 0, "huber": 1, "quadratic": 2}
 FIELD = {"x": 0, "r": 1, "g": 2, "d": 3, "b": 4}
 
@@ -44,11 +47,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                           f"python -m paper_0908_3252_amd.build")
     lib = ctypes.CDLL(path)
     c = ctypes
-    vp, i32, i64, sz, f32 = c.c_void_p, c.c_int32, c.c_int64, c.c_size_t, c.c_float
+    vp, i32, i64, sz, f64 = c.c_void_p, c.c_int32, c.c_int64, c.c_size_t, c.c_double
     sig = {
         "recon_plan_bytes": (sz, [i64, i32, i32, i32]),
         "recon_gram_workspace_bytes": (sz, [i64, i32, i32]),
-        "recon_workspace_bytes": (sz, [i64, i32, i32, i32]),
+        "recon_workspace_bytes": (sz, [i64, i32, i32, i32, i32]),
         "recon_plan": (i32, [vp, i64, i32, i32, i32, vp, sz, vp, c.POINTER(vp)]),
         "recon_plan_info": (i32, [vp, c.POINTER(i64), c.POINTER(i32), c.POINTER(i32),
                                   c.POINTER(i32)]),
@@ -57,13 +60,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_adjoint": (i32, [vp, vp, i32, vp, vp, vp, sz, vp]),
         "recon_forward": (i32, [vp, vp, i32, vp, vp, sz, vp]),
         "recon_gram_apply": (i32, [vp, vp, i32, vp, vp, sz, vp]),
-        "recon_solve": (i32, [vp, vp, i32, f32, f32, i32, i32, vp, i32, vp, sz, vp, vp]),
-        "recon_solve_begin": (i32, [vp, vp, vp, i32, f32, f32, i32, vp, vp, sz, vp]),
+        "recon_solve": (i32, [vp, vp, i32, f64, f64, i32, i32, vp, i32, vp, sz, vp, vp]),
+        "recon_solve_begin": (i32, [vp, vp, vp, i32, f64, f64, i32, vp, vp, sz, vp]),
         "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
         "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
         "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
         "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
-        "recon_pool_admit": (i32, [vp, i32, vp, f32, f32, i32, vp, sz, vp]),
+        "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, i32, vp, sz, vp]),
         "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
         "recon_pool_retire": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "recon_pool_iteration": (i64, [vp, vp]),
@@ -145,7 +148,7 @@ class Plan:
     def workspace(self, B: int):
         """Device workspace for B frames (cached per B)."""
         if B not in self._ws:
-            n = load().recon_workspace_bytes(self.M, self.N, self.L, B)
+            n = load().recon_workspace_bytes(self.M, self.N, self.L, B, self.prec)
             self._ws[B] = (_dev_buf(n), n)
         return self._ws[B]
 
@@ -259,7 +262,7 @@ class Pool:
         self.B = int(B)
         self.phi = phi
         self.stream = stream
-        self.nbytes = lib.recon_workspace_bytes(plan.M, plan.N, plan.L, self.B)
+        self.nbytes = lib.recon_workspace_bytes(plan.M, plan.N, plan.L, self.B, plan.prec)
         with torch.cuda.stream(stream) if stream is not None else _nullctx():
             self.ws = _dev_buf(self.nbytes)
             self.stats = _dev_buf(self.B * STATS_DTYPE.itemsize)

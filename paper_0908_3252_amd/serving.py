@@ -402,7 +402,7 @@ class GpuExecutor(Executor):
 
     def pool_bytes(self, key, slots: int) -> int:
         k, N, L = self.tr[key]
-        return int(self.lib.recon_workspace_bytes(int(k.shape[0]), N, L, slots)) + \
+        return int(self.lib.recon_workspace_bytes(int(k.shape[0]), N, L, slots, self.prec)) + \
             slots * self.recon.STATS_DTYPE.itemsize
 
     def build_plan(self, key):

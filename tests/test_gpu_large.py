@@ -164,3 +164,86 @@ def test_serving_size_adjoint_sampled(N, I, prec):
     tol = serving_adj_tol(prec, k.shape[0], N)
     print(f"  64 sampled entries: rel {e:.2e} (bound {tol:.1e})")
     assert e < tol
+
+
+# The precision form on the 256^2 series: four frames of the 128-frame
+# drifting series (first, two middle, last) solved together; each frame's
+# result is bitwise the one a larger batch gives (batch invariance), so these
+# are the per-frame errors of the series.  With the iteration in FP32 the
+# bound is set by the trajectory, not by the adjoint: after 300 iterations
+# these frames are still ~30% from the minimiser and the iterate amplifies
+# per-step rounding ~1e4-fold (random relative perturbations of 6e-8 per step
+# already move it by 1e-4; the GPU lands at 4e-4..4e-3).  Bound 1e-2 for
+# every adjoint precision with the FP32 iteration.
+SERIES_FRAMES = [0, 42, 85, 127]
+SERIES_BOUND = {recon.FP64: 1e-2, recon.FP32: 1e-2, recon.FP16X3: 1e-2, recon.BF16X3: 1e-2,
+                # FP64 iteration: per-step errors ~1e-15, far under the 1e-4 bar
+                recon.FP64_ITER64: 1e-6}
+
+
+@pytest.fixture(scope="module")
+def series256():
+    frames = []
+    for f in SERIES_FRAMES:
+        p = synthetic.make_frames(3, frames=1, first=f)
+        frames.append(p)
+    p0 = frames[0]
+    x_true = np.concatenate([p.x_true for p in frames])
+    noise = np.concatenate([p.noise for p in frames])
+    y0 = oracle.forward(x_true, p0.k)
+    sig = p0.noise_c * np.abs(y0).max(axis=-1, keepdims=True)
+    y = (y0 + sig * noise).astype(np.complex64)
+    K = oracle.khat(p0.k, p0.N, p0.L)
+    ref = []
+    for i in range(len(frames)):
+        b = oracle.adjoint(y[i], p0.k, p0.N)
+        ref.append(oracle.solve(b, K, p0.lam, p0.delta, p0.iters))
+    return p0, y, np.array(ref)
+
+
+@pytest.mark.parametrize("prec", [recon.FP64_ITER64, recon.FP64, recon.FP32, recon.FP16X3,
+                                  recon.BF16X3])
+def test_precision_form_series256(series256, prec):
+    p, y, ref = series256
+    print(f"series256 frames {SERIES_FRAMES} prec={prec}", flush=True)
+    plan = recon.Plan(p.k, p.N, p.L, prec=prec)
+    plan.gram_kernel()
+    x, st = plan.solve(dev(y), p.lam, p.delta, p.iters)
+    xg = host(x)
+    errs = [rel(xg[i], ref[i]) for i in range(len(SERIES_FRAMES))]
+    print("  per-frame rel-L2 vs FP64 oracle: " +
+          ", ".join(f"f{f}={e:.2e}" for f, e in zip(SERIES_FRAMES, errs)))
+    assert all(s == 0 for s in st["status"])
+    assert max(errs) < SERIES_BOUND[prec]
+
+
+@pytest.mark.parametrize("frame", [85])
+def test_shadow_step_series_frame(frame):
+    """One step of the FP64 oracle from the GPU's own state (after 0, 50 and
+    150 iterations) on a frame of the 256^2 series, against the GPU's next
+    state: the per-iteration deviation of the FP32 iteration."""
+    p = synthetic.make_frames(3, frames=1, first=frame)
+    y0 = oracle.forward(p.x_true, p.k)
+    sig = p.noise_c * np.abs(y0).max(axis=-1, keepdims=True)
+    y = (y0 + sig * p.noise).astype(np.complex64)
+    plan = recon.Plan(p.k, p.N, p.L, prec=recon.FP64)
+    plan.gram_kernel()
+    K = oracle.khat(p.k, p.N, p.L)
+    plan.begin(y=dev(y), lam=p.lam, delta=p.delta)
+    cur = 0
+    for k_it in (0, 50, 150):
+        if k_it > cur:
+            plan.iterate(k_it - cur)
+            cur = k_it
+        st = {f: host(plan.export(f))[0] for f in ("x", "r", "g", "d")}
+        (x1, r1, g1, d1), sc = oracle.solver.step_from_state(
+            st["x"], st["r"], st["g"], st["d"], K, p.lam, p.delta)
+        plan.iterate(1)
+        cur += 1
+        nx = {f: host(plan.export(f))[0] for f in ("x", "r", "g", "d")}
+        errs = {f: rel(nx[f], ref) for f, ref in (("x", x1), ("r", r1), ("g", g1), ("d", d1))}
+        dx = rel(nx["x"] - st["x"], x1 - st["x"])
+        print(f"frame {frame} after {k_it}: " + ", ".join(f"{f} {e:.2e}" for f, e in errs.items())
+              + f"; step (x1 - x) rel {dx:.2e}; alpha {sc['alpha']:.6e} beta {sc['beta']:.6e}"
+              f" restart {sc['restart']}", flush=True)
+        assert max(errs.values()) < 1e-4

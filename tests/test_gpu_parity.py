@@ -251,7 +251,7 @@ def test_zero_data_gives_zero_image():
     x, st = plan.solve(torch.zeros((1, p.M), dtype=torch.complex64, device="cuda"),
                        p.lam, p.delta, 10)
     assert np.all(host(x) == 0)
-    ref = float(np.float32(p.lam)) * 2 * p.N * (p.N - 1) * float(np.float32(p.delta))
+    ref = p.lam * 2 * p.N * (p.N - 1) * p.delta
     assert abs(st["J"][0] - ref) < 1e-9 * ref
     assert st["status"][0] == 0
 

@@ -48,15 +48,16 @@ def standalone(plan, y, lam, delta, iters):
     return x[0], st[0]
 
 
+@pytest.mark.parametrize("prec", [recon.FP64, recon.FP64_ITER64])
 @pytest.mark.parametrize("N,I,S,R,L", [(32, 4, 256, 1.0, 64), (48, 5, 199, 1.0, 128)])
-def test_pool_matches_standalone_bitwise(N, I, S, R, L):
+def test_pool_matches_standalone_bitwise(N, I, S, R, L, prec):
     k, xs = frames_for(N, I, S, R, 6, seed=N)
-    plan = recon.Plan(k, N, L, prec=recon.FP64)
+    plan = recon.Plan(k, N, L, prec=prec)
     plan.gram_kernel()
     y = measured(plan, xs, 0.01, N)
     lam, delta = [0.02, 0.01, 0.03, 0.02, 0.015, 0.05], [0.05, 0.02, 0.1, 0.05, 0.03, 0.05]
     budget = [40, 25, 0, 30, 17, 9]
-    print(f"pool N={N} L={L} slots=3 budgets={budget}", flush=True)
+    print(f"pool N={N} L={L} prec={prec} slots=3 budgets={budget}", flush=True)
     pool = recon.Pool(plan, 3)
     out = {}
 

@@ -39,12 +39,28 @@ def test_size_queries():
     # trajectory + two FP32 phasor tables + twiddles + spectrum
     assert pb >= M * 16 + 2 * M * N * 8 + 512 * 8 + 512 * 512 * 4
     assert lib.recon_plan_bytes(M, N, 0, recon.FP32) == pb  # L = 0 -> 2N rounded to pow2
-    w1 = lib.recon_workspace_bytes(M, N, 512, 1)
-    w8 = lib.recon_workspace_bytes(M, N, 512, 8)
+    w1 = lib.recon_workspace_bytes(M, N, 512, 1, recon.FP32)
+    w8 = lib.recon_workspace_bytes(M, N, 512, 8, recon.FP32)
     assert w1 > 0 and w8 > 0
     # per frame: 8 N x N images + the N x L intermediate
     assert w8 >= 8 * (8 * N * N * 8 + N * 512 * 8)
     assert lib.recon_gram_workspace_bytes(M, N, 512) >= 2 * 512 * 512 * 8
+
+
+def test_fp64_iteration_size_queries():
+    """The FP64 iteration flag: FP64 adjoint and L <= 1024 only; the
+    workspace holds complex128 images and intermediate."""
+    lib = recon.load()
+    M, N = 32768, 256
+    P = recon.FP64_ITER64
+    assert lib.recon_plan_bytes(M, N, 512, P) > lib.recon_plan_bytes(M, N, 512, recon.FP64)
+    assert lib.recon_plan_bytes(M, 40, 2048, P) == 0
+    assert lib.recon_plan_bytes(M, N, 512, recon.FP32 | recon.ITER_FP64) == 0
+    assert lib.recon_workspace_bytes(M, 40, 2048, 1, P) == 0
+    w32 = lib.recon_workspace_bytes(M, N, 512, 8, recon.FP64)
+    w64 = lib.recon_workspace_bytes(M, N, 512, 8, P)
+    # seven N x N images and the N x L intermediate per frame grow 8 -> 16 bytes
+    assert w64 - w32 >= 8 * (7 * N * N * 8 + N * 512 * 8)
 
 
 @pytest.mark.parametrize("M,N,L", [(10, 1, 64), (10, 2000, 4096), (10, 64, 96), (10, 64, 64),
@@ -52,7 +68,7 @@ def test_size_queries():
 def test_invalid_geometry_sizes_are_zero(M, N, L):
     lib = recon.load()
     assert lib.recon_plan_bytes(M, N, L, 0) == 0
-    assert lib.recon_workspace_bytes(M, N, L, 1) == 0
+    assert lib.recon_workspace_bytes(M, N, L, 1, 0) == 0
 
 
 def test_plan_rejects_bad_trajectory_before_any_launch():
