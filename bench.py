@@ -35,7 +35,8 @@ if ROOT not in sys.path:
 import synthetic  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-PRECS = {"fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
+# fp64i: FP64 adjoint and the FP64 iteration (state, FFTs, stencil, spectrum)
+PRECS = {"fp64i": 3 | 16, "fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
 METRIC = "recons/sec + p50/p99 latency at 256^2 spiral, rel-L2<=1e-4 vs FP64 oracle"
 
 
@@ -45,17 +46,19 @@ def log(msg: str):
 
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16x3": 2500.0, "bf16x3": 2500.0}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 CSRC = os.path.join(ROOT, "paper_0908_3252_amd", "csrc")
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 
 
-def kernel_bytes(kind: str, N: int, L: int, B: int) -> float:
+def kernel_bytes(kind: str, N: int, L: int, B: int, es: int = 8) -> float:
     """Algorithmic HBM bytes of one launch over B frames (each array moved
-    once; stencil halo re-reads are not counted)."""
-    img = 8.0 * N * N          # one complex64 image
-    tmat = 8.0 * N * L         # the N x L complex64 intermediate of one frame
+    once; stencil halo re-reads are not counted).  es: bytes of one complex
+    element (8: FP32 iteration, 16: FP64 iteration)."""
+    img = float(es) * N * N    # one image
+    tmat = float(es) * N * L   # the N x L intermediate of one frame
     if kind == "colpass":      # read and write the intermediate, read the spectrum once
-        return B * 2 * tmat + 4.0 * L * L
+        return B * 2 * tmat + (es / 2.0) * L * L
     if kind == "dir_rowfft":   # read x, r, d_old; write d, intermediate
         return B * (4 * img + tmat)
     if kind == "update":       # read intermediate, x, d, r; write x, r
@@ -81,12 +84,13 @@ def csrc_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, kind: str, digest: str):
+def measured_traffic(workload: str, kind: str, digest: str, prec: str = "fp64"):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this workload (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
-    what the counter reads for a plain copy of known size), or None when the
-    kernel sources have changed since the counters were taken."""
-    path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}.txt")
+    this workload and precision (FETCH_SIZE and WRITE_SIZE per dispatch,
+    each scaled by what the counter reads for a plain copy of known size), or
+    None when the kernel sources have changed since the counters were taken."""
+    suffix = "" if prec == "fp64" else f"_{prec}"
+    path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}{suffix}.txt")
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -180,8 +184,9 @@ def main():
     ap.add_argument("--workload", default="series256", choices=list(WORKLOADS))
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
-    ap.add_argument("--prec", default="fp64", choices=list(PRECS),
-                    help="NUDFT contraction precision (fp64: FP64-accumulated adjoint)")
+    ap.add_argument("--prec", default="fp64i", choices=list(PRECS),
+                    help="NUDFT contraction precision (fp64: FP64-accumulated adjoint; "
+                         "fp64i: that adjoint and the iteration in FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=10)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -221,6 +226,7 @@ def main():
     plan = recon.Plan(prob.k, N, L, prec=prec)
     plan.gram_kernel()
     y = synth_batch(plan, prob, B, torch)
+    es = 16 if prec & recon.ITER_FP64 else 8
     k_host = np.ascontiguousarray(prob.k)
     plan_bytes = lib.recon_plan_bytes(M, N, L, prec)
     gws_bytes = lib.recon_gram_workspace_bytes(M, N, L)
@@ -286,22 +292,25 @@ def main():
                    ms_per_step=round(avg_ms * per_step, 3))
         if k in ("adjoint", "forward"):
             fl = kernel_flops(k, N, M, L, B)
-            peak = MFMA_PEAK_TFLOPS[args.prec if k == "adjoint" else
-                                    ("fp32" if args.prec in ("fp32", "fp64") else args.prec)]
+            mp = "fp64" if args.prec == "fp64i" else args.prec
+            peak = MFMA_PEAK_TFLOPS[mp if k == "adjoint" else
+                                    ("fp32" if mp in ("fp32", "fp64") else mp)]
             ach = fl / (avg_ms * 1e-3) / 1e12
             ent.update(bound="mfma", achieved=round(ach, 2), peak=peak, unit="TFLOP/s",
                        frac=round(ach / peak, 4), algorithmic_flops_per_launch=fl)
         else:
-            kb = kernel_bytes(k, N, L, B)
+            kb = kernel_bytes(k, N, L, B, es)
             ach = kb / (avg_ms * 1e-3) / 1e9
             ent.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                        frac=round(ach / HBM_PEAK_GBS, 4), algorithmic_bytes_per_launch=kb)
             if k == "colpass":
                 fl = kernel_flops(k, N, M, L, B)
-                ent["alu_fp32_tflops"] = round(fl / (avg_ms * 1e-3) / 1e12, 2)
-                ent["alu_frac_of_fp32_vector_peak"] = round(
-                    fl / (avg_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4)
-        ent["traffic"] = measured_traffic(args.workload, k, digest)
+                vt = "fp64" if es == 16 else "fp32"
+                vp = FP64_VECTOR_PEAK_TFLOPS if es == 16 else FP32_VECTOR_PEAK_TFLOPS
+                ent[f"alu_{vt}_tflops"] = round(fl / (avg_ms * 1e-3) / 1e12, 2)
+                ent[f"alu_frac_of_{vt}_vector_peak"] = round(
+                    fl / (avg_ms * 1e-3) / 1e12 / vp, 4)
+        ent["traffic"] = measured_traffic(args.workload, k, digest, args.prec)
         rooflines[k] = ent
     dominant = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"])
     roofline = dict(rooflines[dominant])
@@ -332,10 +341,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "fp32 iterations; fp64-accumulated adjoint, fp64 Gram and reductions",
-                  "fp32": "fp32 (fp64 Gram accumulation and reductions)",
-                  "fp16x3": "fp32 iterations; fp16 hi+lo split NUDFT, fp64 Gram and reductions",
-                  "bf16x3": "fp32 iterations; bf16 hi+lo split NUDFT, fp64 Gram and reductions"}[args.prec],
+        "dtype": "f64" if args.prec == "fp64i" else "f32",
+        "precision": {
+            "fp64i": "f64 adjoint, Gram kernel, iterations, FFTs and reductions; f32 forward model",
+            "fp64": "f32 iterations; f64-accumulated adjoint, f64 Gram and reductions",
+            "fp32": "f32 (f64 Gram accumulation and reductions)",
+            "fp16x3": "f32 iterations; fp16 hi+lo split NUDFT, f64 Gram and reductions",
+            "bf16x3": "f32 iterations; bf16 hi+lo split NUDFT, f64 Gram and reductions"}[args.prec],
         "data": "synthetic",
         "config": {"workload": (f"256x256 spiral M={M} (16 interleaves, 2x angular "
                                 f"undersampling), hyperbolic delta={prob.delta}, "

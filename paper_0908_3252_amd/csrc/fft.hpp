@@ -170,22 +170,65 @@ __device__ __forceinline__ void team_sync() {
   }
 }
 
+// LDS of one team's exchange buffers, in elements of C.  FP32 values are
+// exchanged whole; FP64 values one component at a time (8-byte halves), so
+// the buffer is half as large and the access pattern is the one of the FP32
+// transform.  Multi-wave teams need two buffers (block barriers, no
+// write-after-read wait between consecutive exchanges).
+template <int L, typename C>
+struct FftLds {
+  static constexpr bool SPLIT = sizeof(C) == 16;
+  static constexpr int BUFS = FftSync<L>::WAVE_LOCAL ? 1 : 2;
+  static constexpr int TEAM = SPLIT ? BUFS * FftShape<L>::PAD / 2 : BUFS * FftShape<L>::PAD;
+};
+
+template <int L, typename C>
+constexpr int fft_team_lds() {
+  return FftLds<L, C>::TEAM;
+}
+
+// Exchange after pass P: value e goes to position pos[e] and comes back as
+// element t + e*T.  tb: the team's buffers.
+template <int L, int P, typename C>
+__device__ __forceinline__ void fft_exchange(C (&v)[8], const int (&pos)[8], int t, C* tb) {
+  using S = FftShape<L>;
+  constexpr bool WL = FftSync<L>::WAVE_LOCAL;
+  if constexpr (FftLds<L, C>::SPLIT) {
+    double* b0 = reinterpret_cast<double*>(tb);
+    double* b1 = b0 + (WL ? 0 : S::PAD);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b0[lpad(pos[e])] = v[e].x;
+    team_sync<L>();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e].x = b0[lpad(t + e * S::T)];
+    if constexpr (WL) team_sync<L>();  // reads before the writes of the other half
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b1[lpad(pos[e])] = v[e].y;
+    team_sync<L>();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e].y = b1[lpad(t + e * S::T)];
+    if constexpr (WL) team_sync<L>();  // reads before the next writes
+  } else {
+    C* buf = (WL || !(P & 1)) ? tb : tb + S::PAD;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
+    team_sync<L>();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = buf[lpad(t + e * S::T)];
+    if constexpr (WL) team_sync<L>();  // reads before next writes
+  }
+}
+
 template <int L, bool INV, bool HALF_IN, int P, int NS, typename C>
-__device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* buf0, C* buf1, const C* tw) {
+__device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* tb, const C* tw) {
   using S = FftShape<L>;
   constexpr int R = (P == 0 && S::REM) ? (1 << S::REM) : 8;
   constexpr bool HALF = HALF_IN && (P == 0);
   int pos[8];
   fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
   if constexpr (P + 1 < S::NP) {
-    C* buf = (FftSync<L>::WAVE_LOCAL || !(P & 1)) ? buf0 : buf1;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
-    team_sync<L>();
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = buf[lpad(t + e * S::T)];
-    if constexpr (FftSync<L>::WAVE_LOCAL) team_sync<L>();  // reads before next writes
-    fft_passes<L, INV, HALF_IN, P + 1, NS * R>(v, t, buf0, buf1, tw);
+    fft_exchange<L, P>(v, pos, t, tb);
+    fft_passes<L, INV, HALF_IN, P + 1, NS * R>(v, t, tb, tw);
   }
   // Last pass: j < L/R = NS, so pos[e] = t + e*T and v is already in the
   // strided output layout.
@@ -193,22 +236,15 @@ __device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* buf0, C* buf1, c
 
 // Full transform.  For L > 512 every thread of the block must call this
 // (block barriers); for L <= 512 only the team's own wavefront is involved.
-// buf0/buf1: this team's LDS buffers of PAD entries (buf1 unused when the
-// team is wave-local; it may then alias buf0); tw: the per-pass LDS twiddle
-// table built by load_twiddles.
+// tb: this team's exchange buffers (fft_team_lds<L, C>() elements of LDS);
+// tw: the per-pass LDS twiddle table built by load_twiddles.
 template <int L, bool INV, bool HALF_IN, typename C>
-__device__ __forceinline__ void fft_team(C (&v)[8], int t, C* buf0, C* buf1, const C* tw) {
+__device__ __forceinline__ void fft_team(C (&v)[8], int t, C* tb, const C* tw) {
   if (HALF_IN) {
 #pragma unroll
     for (int e = 4; e < 8; ++e) v[e] = cmk<C>(0, 0);
   }
-  fft_passes<L, INV, HALF_IN, 0, 1>(v, t, buf0, buf1, tw);
-}
-
-// LDS entries one team needs for its exchange buffers.
-template <int L>
-constexpr int fft_team_lds() {
-  return (FftSync<L>::WAVE_LOCAL ? 1 : 2) * FftShape<L>::PAD;
+  fft_passes<L, INV, HALF_IN, 0, 1>(v, t, tb, tw);
 }
 
 // Build the per-pass twiddle table in LDS (TWN <= L entries) from the plan's

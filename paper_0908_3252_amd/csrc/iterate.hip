@@ -65,9 +65,10 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   using R = real_t<C>;
   constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
   constexpr int XT = (ROWS + 3) * W;      // x rows n0-1 .. n0+ROWS+1
-  constexpr int DT = (ROWS + 1) * W;      // d rows n0 .. n0+ROWS
-  constexpr int FFTB = ROWS * fft_team_lds<L>();
-  constexpr int SH = (XT + DT > FFTB) ? XT + DT : FFTB;
+  constexpr int DT = (ROWS + 1) * W;      // d rows n0 .. n0+ROWS (over the x tile)
+  constexpr int FFTB = ROWS * fft_team_lds<L, C>();
+  constexpr int SH = (XT > FFTB) ? XT : FFTB;
+  static_assert(DT <= XT, "d tile aliases the x tile");
   // halo element j of a thread: row j / W, column j % W (W a power of two)
   constexpr int HX = (3 * W + 255) / 256;  // x halo elements per thread (3 rows)
   constexpr int HD = (W + 255) / 256;      // r, d halo elements per thread (1 row)
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   __shared__ C sh[SH];
   __shared__ double red[2 * 4];
   __shared__ R sbeta;
-  C* Xt = sh;       // tile row i <-> image row n0 - 1 + i (stride N)
-  C* Dt = sh + XT;  // tile row i <-> image row n0 + i
+  C* Xt = sh;  // tile row i <-> image row n0 - 1 + i (stride N)
+  C* Dt = sh;  // after the gradients: tile row i <-> image row n0 + i
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 
   // -- gradient and new direction: own rows and the halo row n0 + ROWS
   double gd = 0.0;
-  C dn[EPT];
+  C dn[EPT], dh[HD];
   R wdn[EPT], wrt[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -163,7 +164,6 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
                                        wrt[e]);
       const C g = grad_from(ro[e], div, lam);
       dn[e] = cmk<C>(rfma(bf, dv[e].x, -g.x), rfma(bf, dv[e].y, -g.y));
-      Dt[team * N + m] = dn[e];
       d_new[fo + (size_t)n * N + m] = dn[e];
       gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
     }
@@ -177,8 +177,21 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
         const C* mid = Xt + (ROWS + 1) * N;
         const C div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
         const C g = grad_from(hr[s], div, lam);
-        Dt[ROWS * N + m] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
+        dh[s] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
       }
+    }
+  }
+  __syncthreads();  // every read of the x tile is done: the d tile replaces it
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) Dt[team * N + m] = dn[e];
+  }
+  if (n0 + ROWS < N) {
+#pragma unroll
+    for (int s = 0; s < HD; ++s) {
+      const int m = threadIdx.x + s * 256;
+      if (m < N) Dt[ROWS * N + m] = dh[s];
     }
   }
   __syncthreads();
@@ -213,10 +226,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   C val[8];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) val[e] = dn[e];
-  fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L>(),
-                           sh + team * fft_team_lds<L>() +
-                               (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD),
-                           tw);
+  fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L, C>(), tw);
   if (n < N) {
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
@@ -235,9 +245,14 @@ __global__ __launch_bounds__(256) void k_update(
   using R = real_t<C>;
   constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
   constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
-  constexpr int FFTB = ROWS * fft_team_lds<L>();
-  constexpr int SH = (2 * XT > FFTB) ? 2 * XT : FFTB;
+  constexpr int FFTB = ROWS * fft_team_lds<L, C>();
   constexpr int HX = (2 * W + 255) / 256;  // halo elements per thread (2 rows, j -> j/W, j%W)
+  // SEP: the x tile and the transform buffers are separate, and the x work
+  // runs before the inverse transform (the halo and old-x registers are free
+  // by then): the FP64 form at L <= 512, where registers bound occupancy.
+  // Otherwise they share LDS and the transform runs first.
+  constexpr bool SEP = sizeof(C) == 16 && L <= 512;
+  constexpr int SH = SEP ? XT + FFTB : (XT > FFTB ? XT : FFTB);
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;
@@ -245,8 +260,8 @@ __global__ __launch_bounds__(256) void k_update(
   __shared__ C sh[SH];
   __shared__ double red[4 * 4];
   __shared__ R salpha;
-  C* Xo = sh;       // x at the start of the iteration; row i <-> image row n0-1+i
-  C* Xn = sh + XT;  // x + alpha d
+  C* Xt = sh;                      // x, then x + alpha d (in place); row i <-> image row n0-1+i
+  C* fb = SEP ? sh + XT : sh;      // exchange buffers of the row transforms
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -293,36 +308,60 @@ __global__ __launch_bounds__(256) void k_update(
     const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
     if (threadIdx.x == 0) salpha = (R)alpha;
   }
-  __syncthreads();  // twiddles, step length
-  const R af = salpha;
 
-  // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
-  fft_team<L, true, false>(val, t, sh + team * fft_team_lds<L>(),
-                           sh + team * fft_team_lds<L>() +
-                               (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD),
-                           tw);
-  __syncthreads();  // FFT buffers become the x tiles
+  if constexpr (!SEP) {
+    __syncthreads();  // twiddles, step length
+    fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
+    __syncthreads();  // the transform buffers become the x tile
+  }
 
+  // Old x: tile, divergence and gradient at the start of the iteration.
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
-    if (n < N && m < N) {
-      Xo[(team + 1) * N + m] = xo[e];
-      Xn[(team + 1) * N + m] = c_axpy(af, dv[e], xo[e]);
-    }
+    if (n < N && m < N) Xt[(team + 1) * N + m] = xo[e];
   }
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
     const int sel = j / W, m = j % W;
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
-    if (j < 2 * W && m < N && img >= 0 && img < N) {
-      const int o = (img - n0 + 1) * N + m;
-      Xo[o] = hx[s];
-      Xn[o] = c_axpy(af, hd[s], hx[s]);
+    if (j < 2 * W && m < N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
+  }
+  __syncthreads();  // x tile, twiddles, step length
+  const R af = salpha;
+  C go[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    go[e] = cmk<C>(0, 0);
+    if (n < N && m < N) {
+      const C* mo = Xt + (team + 1) * N;
+      const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
+                                      n + 1 < N ? mo + N : nullptr, m, N, delta);
+      go[e] = grad_from(ro[e], div_o, lam);
     }
   }
-  __syncthreads();
+  __syncthreads();  // every read of the old x is done
+
+  // New x = x + alpha d, in place (each thread rewrites the entries it wrote).
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int m = t + e * TT;
+    if (n < N && m < N) Xt[(team + 1) * N + m] = c_axpy(af, dv[e], xo[e]);
+  }
+#pragma unroll
+  for (int s = 0; s < HX; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / W, m = j % W;
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+    if (j < 2 * W && m < N && img >= 0 && img < N)
+      Xt[(img - n0 + 1) * N + m] = c_axpy(af, hd[s], hx[s]);
+  }
+
+  // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
+  if constexpr (SEP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
+  __syncthreads();  // new x tile complete
 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -330,22 +369,18 @@ __global__ __launch_bounds__(256) void k_update(
     const int m = t + e * TT;
     if (n < N && m < N) {
       const size_t idx = fo + (size_t)n * N + m;
-      const C* mo = Xo + (team + 1) * N;
-      const C* mn = Xn + (team + 1) * N;
-      const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
-                                      n + 1 < N ? mo + N : nullptr, m, N, delta);
+      const C* mn = Xt + (team + 1) * N;
       const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
                                       n + 1 < N ? mn + N : nullptr, m, N, delta);
-      const C go = grad_from(ro[e], div_o, lam);
       const C rn = c_axpy(af, val[e], ro[e]);
       const C gn = grad_from(rn, div_n, lam);
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
       acc[0] += gx * gx + gy * gy;
-      acc[1] += gx * (double)go.x + gy * (double)go.y;
+      acc[1] += gx * (double)go[e].x + gy * (double)go[e].y;
       acc[2] += gx * (double)dv[e].x + gy * (double)dv[e].y;
-      acc[3] += (double)go.x * (double)go.x + (double)go.y * (double)go.y;
+      acc[3] += (double)go[e].x * (double)go[e].x + (double)go[e].y * (double)go[e].y;
     }
   }
   block_sum<4>(acc, red);

@@ -22,14 +22,15 @@ __device__ __forceinline__ float pen_weight(float s2, float delta) {
   }
 }
 
-// FP64 weights (the FP64 iteration): correctly rounded square root and
-// division.
+// FP64 weights (the FP64 iteration): the FP64 reciprocal square root
+// (hardware estimate plus one refinement, within about an ulp) instead of a
+// square root followed by a division, about a fifth of the instructions.
 template <int PHI>
 __device__ __forceinline__ double pen_weight(double s2, double delta) {
   if constexpr (PHI == 0) {
-    return 1.0 / sqrt(fma(delta, delta, s2));
+    return rsqrt(fma(delta, delta, s2));
   } else if constexpr (PHI == 1) {
-    return (s2 <= delta * delta) ? 2.0 : 2.0 * delta / sqrt(s2);
+    return (s2 <= delta * delta) ? 2.0 : 2.0 * delta * rsqrt(s2);
   } else {
     return 2.0;
   }

@@ -22,12 +22,8 @@ namespace recon {
 
 // Exchange buffers of one team inside a block-shared array.
 template <int L, typename C>
-__device__ __forceinline__ C* team_buf0(C* base, int team) {
-  return base + team * fft_team_lds<L>();
-}
-template <int L, typename C>
-__device__ __forceinline__ C* team_buf1(C* base, int team) {
-  return team_buf0<L>(base, team) + (FftSync<L>::WAVE_LOCAL ? 0 : FftShape<L>::PAD);
+__device__ __forceinline__ C* team_buf(C* base, int team) {
+  return base + team * fft_team_lds<L, C>();
 }
 
 // ----------------------------------------------------------------- row pass
@@ -38,7 +34,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
   using S = FftShape<L>;
   constexpr int ROWS = 256 / S::T;
   __shared__ C tw[L];
-  __shared__ C bufs[ROWS * fft_team_lds<L>()];
+  __shared__ C bufs[ROWS * fft_team_lds<L, C>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
@@ -51,7 +47,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
     val[e] = (n < N && p < N) ? row[p] : cmk<C>(0, 0);
   }
   __syncthreads();
-  fft_team<L, false, true>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
+  fft_team<L, false, true>(val, t, team_buf<L>(bufs, team), tw);
   if (n < N) {
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
@@ -85,14 +81,16 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   constexpr int COLS = CC::COLS;
   constexpr int TEAMS = CC::TEAMS;
   constexpr int NT = CC::THREADS;
-  // Column-major tile: column c at tile[c * TS + n].  TS = L/2 + 4 makes the
-  // column stride 8 words mod 64 banks, so both the row-wise global staging
-  // (consecutive threads -> consecutive columns) and the column-wise FFT
-  // gathers (consecutive threads -> consecutive rows) are conflict-free.
-  constexpr int TS = L / 2 + 4;
+  // Column-major tile: column c at tile[c * TS + n].  TS = L/2 + 2 puts
+  // consecutive columns 4 (FP32) or 8 (FP64) 4-byte banks apart, so the 16
+  // FP32 (8 FP64) columns of one row that the row-wise staging touches per
+  // LDS cycle (consecutive threads -> consecutive columns) hit distinct
+  // banks; the column-wise FFT gathers (consecutive threads -> consecutive
+  // rows) are unit-stride.
+  constexpr int TS = L / 2 + 2;
   __shared__ C tw[L];
   __shared__ C tile[COLS * TS];
-  __shared__ C bufs[TEAMS * fft_team_lds<L>()];
+  __shared__ C bufs[TEAMS * fft_team_lds<L, C>()];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
   const int q0 = blockIdx.x * COLS;
@@ -117,8 +115,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   }
   __syncthreads();
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
-  C* b0 = team_buf0<L>(bufs, team);
-  C* b1 = team_buf1<L>(bufs, team);
+  C* tb = team_buf<L>(bufs, team);
   // Wave-local teams touch only their own columns and buffers: no block
   // barrier inside the loop.  Multi-wave teams synchronise inside the FFT.
 #pragma unroll 1
@@ -131,7 +128,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
       const int p = t + e * S::T;
       val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
-    fft_team<L, false, true>(val, t, b0, b1, tw);
+    fft_team<L, false, true>(val, t, tb, tw);
     const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
     R acc = 0;
 #pragma unroll
@@ -142,7 +139,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     }
     if (active) dqd += (double)acc;
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
-    fft_team<L, true, false>(val, t, b0, b1, tw);
+    fft_team<L, true, false>(val, t, tb, tw);
     if (active) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -175,7 +172,7 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
   constexpr int ROWS = 256 / S::T;
   if (fp && kit >= fp[blockIdx.y].stop_at) return;
   __shared__ C tw[L];
-  __shared__ C bufs[ROWS * fft_team_lds<L>()];
+  __shared__ C bufs[ROWS * fft_team_lds<L, C>()];
   const int f = blockIdx.y;
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
@@ -185,7 +182,7 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
 #pragma unroll
   for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : cmk<C>(0, 0);
   __syncthreads();
-  fft_team<L, true, false>(val, t, team_buf0<L>(bufs, team), team_buf1<L>(bufs, team), tw);
+  fft_team<L, true, false>(val, t, team_buf<L>(bufs, team), tw);
   if (n < N) {
     const size_t ro = ((size_t)f * N + n) * N;
 #pragma unroll

@@ -511,7 +511,8 @@ def make_workload(count: int, seed: int = 4):
     return base, traj, plans
 
 
-PRECS = {"fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
+# fp64i: FP64 adjoint and FP64 iteration (state, FFTs, stencil, spectrum)
+PRECS = {"fp64i": 3 | 16, "fp64": 3, "fp32": 0, "fp16x3": 2, "bf16x3": 1}
 
 
 def serve(rate: float, workload, warmup_frac: float = 0.1, hbm_budget: Optional[int] = None,
@@ -594,7 +595,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="continuous-batching reconstruction server")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000")
     ap.add_argument("--precs", default="fp64",
-                    help="comma list of NUDFT precisions (fp64, fp32, fp16x3, bf16x3); with "
+                    help="comma list of precisions (fp64i, fp64, fp32, fp16x3, bf16x3); with "
                          "several, each later one is compared with the first's results")
     ap.add_argument("--count", type=int, default=2200)
     ap.add_argument("--seed", type=int, default=4)
