@@ -81,16 +81,23 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   constexpr int COLS = CC::COLS;
   constexpr int TEAMS = CC::TEAMS;
   constexpr int NT = CC::THREADS;
-  // Column-major tile: column c at tile[c * TS + n].  TS = L/2 + 2 puts
+  // Column-major tile: column c at tile[c * TS + n].  TS = 2 (mod 16) puts
   // consecutive columns 4 (FP32) or 8 (FP64) 4-byte banks apart, so the 16
   // FP32 (8 FP64) columns of one row that the row-wise staging touches per
   // LDS cycle (consecutive threads -> consecutive columns) hit distinct
   // banks; the column-wise FFT gathers (consecutive threads -> consecutive
   // rows) are unit-stride.
-  constexpr int TS = L / 2 + 2;
+  // INCOL (FP64, wave-local teams): while a team transforms its column, the
+  // column's values are in registers, so the column itself (TS >= the
+  // component-wise exchange buffer) serves as the team's exchange buffer.
+  constexpr bool INCOL = sizeof(C) == 16 && FftSync<L>::WAVE_LOCAL;
+  constexpr int TS0 = L / 2 + 2;
+  constexpr int TS = (INCOL && fft_team_lds<L, C>() > TS0)
+                         ? (fft_team_lds<L, C>() + 15) / 16 * 16 + 2 : TS0;
+  constexpr int NBUF = INCOL ? 1 : TEAMS * fft_team_lds<L, C>();
   __shared__ C tw[L];
   __shared__ C tile[COLS * TS];
-  __shared__ C bufs[TEAMS * fft_team_lds<L, C>()];
+  __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
   const int q0 = blockIdx.x * COLS;
@@ -115,20 +122,24 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   }
   __syncthreads();
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
-  C* tb = team_buf<L>(bufs, team);
+  C* tb = INCOL ? nullptr : team_buf<L>(bufs, team);
   // Wave-local teams touch only their own columns and buffers: no block
   // barrier inside the loop.  Multi-wave teams synchronise inside the FFT.
 #pragma unroll 1
   for (int c0 = 0; c0 < COLS; c0 += TEAMS) {
     const int c = c0 + team;
     const bool active = c < COLS;  // uniform per team
+    // INCOL teams exchange through their own column: a team without a column
+    // skips the round (wave-local teams, so no barrier is missed).
+    if (INCOL && !active) continue;
     C val[8];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int p = t + e * S::T;
       val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
-    fft_team<L, false, true>(val, t, tb, tw);
+    // (INCOL: the reads above precede the exchange writes within the wave)
+    fft_team<L, false, true>(val, t, INCOL ? tile + c * TS : tb, tw);
     const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
     R acc = 0;
 #pragma unroll
@@ -139,7 +150,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     }
     if (active) dqd += (double)acc;
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
-    fft_team<L, true, false>(val, t, tb, tw);
+    fft_team<L, true, false>(val, t, INCOL ? tile + c * TS : tb, tw);
     if (active) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
