@@ -594,7 +594,7 @@ def main(argv=None):
     import sys
     ap = argparse.ArgumentParser(description="continuous-batching reconstruction server")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000")
-    ap.add_argument("--precs", default="fp64",
+    ap.add_argument("--precs", default="fp64i",
                     help="comma list of precisions (fp64i, fp64, fp32, fp16x3, bf16x3); with "
                          "several, each later one is compared with the first's results")
     ap.add_argument("--count", type=int, default=2200)
