@@ -1,21 +1,23 @@
 // Stockham FFT of power-of-two length L held in registers by a team of
-// T = L/8 threads (8 values per thread), with LDS exchanges between passes.
+// T = L/V threads (V = 16 values per thread for L = 1024, so that such a
+// team is still one wavefront, 8 otherwise), with LDS exchanges between
+// passes.
 //
-// Layout: on entry thread t of the team holds v[e] = X[t + e*T], e = 0..7;
-// on exit it holds v[e] = Xhat[t + e*T] in the same strided layout, so both
-// the first pass's loads and the last pass's stores are unit-stride across
-// the team (coalesced in global memory, conflict-free in LDS).
+// Layout: on entry thread t of the team holds v[e] = X[t + e*T], e < V; on
+// exit it holds v[e] = Xhat[t + e*T] in the same strided layout, so both the
+// first pass's loads and the last pass's stores are unit-stride across the
+// team (coalesced in global memory, conflict-free in LDS).
 //
 // Passes (self-sorting Stockham, decimation in time): one leading radix-2 or
 // radix-4 pass when log2(L) is not a multiple of 3, then radix-8 passes.  A
-// pass of radix R over span Ns treats butterfly j = t + u*T (u < 8/R) with
-// inputs X[j + r*L/R] = v[u + r*(8/R)], twiddles W_{Ns R}^{r k} (k = j mod
+// pass of radix R over span Ns treats butterflies j = t + u*T (u < V/R) with
+// inputs X[j + r*L/R] = v[u + r*(V/R)], twiddles W_{Ns R}^{r k} (k = j mod
 // Ns), an R-point DFT, and outputs at (j - k) R + k + r Ns.
 //
 // Pruning for the zero-padded Gram apply: HALF_IN declares X[i] = 0 for
-// i >= L/2 (v[4..7] = 0 on entry, folded out of the first pass); a caller
-// that only needs outputs i < L/2 reads only v[0..3], and the compiler drops
-// the unused half of the last pass.
+// i >= L/2 (v[V/2..V-1] = 0 on entry, folded out of the first pass); a
+// caller that only needs outputs i < L/2 reads only v[0..V/2-1], and the
+// compiler drops the unused half of the last pass.
 //
 // Forward transform: Xhat[p] = sum_i X[i] exp(-2 pi i p / L); inverse: the
 // conjugate kernel, unnormalised.
@@ -29,7 +31,8 @@ struct FftShape {
   static constexpr int LOG = (L == 64) ? 6 : (L == 128) ? 7 : (L == 256) ? 8
                             : (L == 512) ? 9 : (L == 1024) ? 10 : (L == 2048) ? 11 : -1;
   static_assert(LOG > 0, "unsupported FFT length");
-  static constexpr int T = L / 8;
+  static constexpr int V = (L == 1024) ? 16 : 8;  // values per thread
+  static constexpr int T = L / V;                  // threads per team
   static constexpr int NR8 = LOG / 3;
   static constexpr int REM = LOG % 3;
   static constexpr int NP = NR8 + (REM ? 1 : 0);
@@ -119,9 +122,10 @@ __device__ __forceinline__ void dft(C* a) {
 
 // One Stockham pass; returns the output positions of v[e] in pos[e].
 template <int L, int R, int NS, bool INV, bool HALF, typename C>
-__device__ __forceinline__ void fft_pass(C (&v)[8], int t, const C* tw, int (&pos)[8]) {
-  constexpr int NB = 8 / R;
-  constexpr int T = L / 8;
+__device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const C* tw,
+                                         int (&pos)[FftShape<L>::V]) {
+  constexpr int NB = FftShape<L>::V / R;
+  constexpr int T = FftShape<L>::T;
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int j = t + u * T;
@@ -190,41 +194,42 @@ constexpr int fft_team_lds() {
 // Exchange after pass P: value e goes to position pos[e] and comes back as
 // element t + e*T.  tb: the team's buffers.
 template <int L, int P, typename C>
-__device__ __forceinline__ void fft_exchange(C (&v)[8], const int (&pos)[8], int t, C* tb) {
+__device__ __forceinline__ void fft_exchange(C (&v)[FftShape<L>::V],
+                                             const int (&pos)[FftShape<L>::V], int t, C* tb) {
   using S = FftShape<L>;
   constexpr bool WL = FftSync<L>::WAVE_LOCAL;
   if constexpr (FftLds<L, C>::SPLIT) {
     double* b0 = reinterpret_cast<double*>(tb);
     double* b1 = b0 + (WL ? 0 : S::PAD);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) b0[lpad(pos[e])] = v[e].x;
+    for (int e = 0; e < S::V; ++e) b0[lpad(pos[e])] = v[e].x;
     team_sync<L>();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e].x = b0[lpad(t + e * S::T)];
+    for (int e = 0; e < S::V; ++e) v[e].x = b0[lpad(t + e * S::T)];
     if constexpr (WL) team_sync<L>();  // reads before the writes of the other half
 #pragma unroll
-    for (int e = 0; e < 8; ++e) b1[lpad(pos[e])] = v[e].y;
+    for (int e = 0; e < S::V; ++e) b1[lpad(pos[e])] = v[e].y;
     team_sync<L>();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e].y = b1[lpad(t + e * S::T)];
+    for (int e = 0; e < S::V; ++e) v[e].y = b1[lpad(t + e * S::T)];
     if constexpr (WL) team_sync<L>();  // reads before the next writes
   } else {
     C* buf = (WL || !(P & 1)) ? tb : tb + S::PAD;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) buf[lpad(pos[e])] = v[e];
+    for (int e = 0; e < S::V; ++e) buf[lpad(pos[e])] = v[e];
     team_sync<L>();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = buf[lpad(t + e * S::T)];
+    for (int e = 0; e < S::V; ++e) v[e] = buf[lpad(t + e * S::T)];
     if constexpr (WL) team_sync<L>();  // reads before next writes
   }
 }
 
 template <int L, bool INV, bool HALF_IN, int P, int NS, typename C>
-__device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* tb, const C* tw) {
+__device__ __forceinline__ void fft_passes(C (&v)[FftShape<L>::V], int t, C* tb, const C* tw) {
   using S = FftShape<L>;
   constexpr int R = (P == 0 && S::REM) ? (1 << S::REM) : 8;
   constexpr bool HALF = HALF_IN && (P == 0);
-  int pos[8];
+  int pos[S::V];
   fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
   if constexpr (P + 1 < S::NP) {
     fft_exchange<L, P>(v, pos, t, tb);
@@ -239,10 +244,10 @@ __device__ __forceinline__ void fft_passes(C (&v)[8], int t, C* tb, const C* tw)
 // tb: this team's exchange buffers (fft_team_lds<L, C>() elements of LDS);
 // tw: the per-pass LDS twiddle table built by load_twiddles.
 template <int L, bool INV, bool HALF_IN, typename C>
-__device__ __forceinline__ void fft_team(C (&v)[8], int t, C* tb, const C* tw) {
+__device__ __forceinline__ void fft_team(C (&v)[FftShape<L>::V], int t, C* tb, const C* tw) {
   if (HALF_IN) {
 #pragma unroll
-    for (int e = 4; e < 8; ++e) v[e] = cmk<C>(0, 0);
+    for (int e = FftShape<L>::V / 2; e < FftShape<L>::V; ++e) v[e] = cmk<C>(0, 0);
   }
   fft_passes<L, INV, HALF_IN, 0, 1>(v, t, tb, tw);
 }

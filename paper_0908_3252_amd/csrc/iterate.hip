@@ -12,8 +12,9 @@
 //                  x += alpha d, r += alpha Qd, g_new = 2 r + lam grad R(x),
 //                  partials |g_new|^2, Re<g_new, g>, Re<g_new, d>, |g|^2
 //
-// A block owns ROWS = 2048 / L image rows, one FFT team (L/8 threads) per
-// row; thread t of the team owns the pixels m = t + e L/8 (e < 4) of its row,
+// A block owns ROWS = 256 / T image rows, one FFT team (T = L/V threads, V
+// values each) per row; thread t of the team owns the pixels m = t + e T
+// (e < V/2) of its row,
 // which is exactly the layout the FFT team takes in and gives out, so pixel
 // data, the transform and the update stay in registers.  Every global load
 // of a thread (own pixels and its share of the one- or two-row halos that
@@ -28,10 +29,10 @@ namespace recon {
 
 template <int L>
 struct RowCfg {
-  static constexpr int TT = L / 8;        // threads per row team
+  static constexpr int TT = FftShape<L>::T;  // threads per row team
   static constexpr int ROWS = 256 / TT;   // rows per block
   static constexpr int W = L / 2;         // widest image row (N <= L/2)
-  static constexpr int EPT = W / TT;      // own pixels per thread (4)
+  static constexpr int EPT = W / TT;      // own pixels per thread (V / 2)
 };
 
 // Logical (row block, frame) of this workgroup.  Workgroups are dispatched
@@ -223,14 +224,14 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   }
 
   // -- row FFT of d (team layout in = own pixels)
-  C val[8];
+  C val[FftShape<L>::V];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) val[e] = dn[e];
   fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L, C>(), tw);
   if (n < N) {
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) out[t + e * TT] = val[e];
+    for (int e = 0; e < FftShape<L>::V; ++e) out[t + e * TT] = val[e];
   }
 }
 
@@ -268,11 +269,11 @@ __global__ __launch_bounds__(256) void k_update(
   const int n = n0 + team;
 
   // -- loads: the transformed row, own pixels, halo rows
-  C val[8];
+  C val[FftShape<L>::V];
   {
     const C* row = T + ((size_t)f * N + (n < N ? n : 0)) * L;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) val[e] = row[t + e * TT];
+    for (int e = 0; e < FftShape<L>::V; ++e) val[e] = row[t + e * TT];
   }
   C xo[EPT], dv[EPT], ro[EPT];
 #pragma unroll
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_update(
       Xt[(img - n0 + 1) * N + m] = c_axpy(af, hd[s], hx[s]);
   }
 
-  // -- Qd row: inverse FFT, first N outputs (v[e], e < 4, are pixels t + e L/8)
+  // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
   if constexpr (SEP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
   __syncthreads();  // new x tile complete
 

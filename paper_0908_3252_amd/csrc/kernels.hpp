@@ -20,8 +20,9 @@ struct FrameParam {
   int32_t pad;
 };
 
-// Rows handled by one 256-thread block of the row-FFT kernels.
-inline int fft_rows_per_block(int L) { return 2048 / L; }
+// Rows handled by one 256-thread block of the row-FFT kernels: one team of
+// L/V threads per row (V = 16 values per thread at L = 1024, 8 otherwise).
+inline int fft_rows_per_block(int L) { return (L == 1024 ? 4096 : 2048) / L; }
 // Columns handled by one block of the column kernel (f64: the FP64 form).
 int fft_cols_per_block(int L, bool f64);
 

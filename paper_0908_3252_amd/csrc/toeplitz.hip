@@ -39,10 +39,10 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
   load_twiddles<L>(tw, twg);
-  C val[8];
+  C val[S::V];
   const C* row = v + ((size_t)f * N + n) * N;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < S::V / 2; ++e) {
     const int p = t + e * S::T;
     val[e] = (n < N && p < N) ? row[p] : cmk<C>(0, 0);
   }
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
   if (n < N) {
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) out[t + e * S::T] = val[e];
+    for (int e = 0; e < S::V; ++e) out[t + e * S::T] = val[e];
   }
 }
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
 // block (and the threads at L = 512) so that the tile stays within LDS.
 template <int L, int ES = 1>
 struct ColCfg {
-  static constexpr int T = L / 8;
+  static constexpr int T = FftShape<L>::T;
   static constexpr int THREADS = (L == 512 && ES == 1) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
   static constexpr int COLS = ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
@@ -132,9 +132,9 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     // INCOL teams exchange through their own column: a team without a column
     // skips the round (wave-local teams, so no barrier is missed).
     if (INCOL && !active) continue;
-    C val[8];
+    C val[S::V];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < S::V / 2; ++e) {
       const int p = t + e * S::T;
       val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
     R acc = 0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < S::V; ++e) {
       const R kv = kq[t + e * S::T];
       acc = rfma(kv, c_abs2(val[e]), acc);
       val[e] = c_scale(val[e], kv);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     fft_team<L, true, false>(val, t, INCOL ? tile + c * TS : tb, tw);
     if (active) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < S::V / 2; ++e) {
         const int p = t + e * S::T;
         if (p < N) tile[c * TS + p] = val[e];
       }
@@ -188,16 +188,16 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   const int n = blockIdx.x * ROWS + team;
   load_twiddles<L>(tw, twg);
-  C val[8];
+  C val[S::V];
   const C* row = T + ((size_t)f * N + n) * L;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) val[e] = (n < N) ? row[t + e * S::T] : cmk<C>(0, 0);
+  for (int e = 0; e < S::V; ++e) val[e] = (n < N) ? row[t + e * S::T] : cmk<C>(0, 0);
   __syncthreads();
   fft_team<L, true, false>(val, t, team_buf<L>(bufs, team), tw);
   if (n < N) {
     const size_t ro = ((size_t)f * N + n) * N;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < S::V / 2; ++e) {
       const int p = t + e * S::T;
       if (p < N) out[ro + p] = val[e];
     }
