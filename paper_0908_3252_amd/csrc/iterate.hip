@@ -33,6 +33,7 @@ struct RowCfg {
   static constexpr int ROWS = 256 / TT;   // rows per block
   static constexpr int W = L / 2;         // widest image row (N <= L/2)
   static constexpr int EPT = W / TT;      // own pixels per thread (V / 2)
+  static constexpr int HX2 = (2 * W + 255) / 256;  // two-row halo elements per thread
 };
 
 // Logical (row block, frame) of this workgroup.  Workgroups are dispatched
@@ -236,6 +237,31 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
 }
 
 // ------------------------------------------------ inverse rows + update
+// Loads of the update kernel: a thread's own pixels of one image, and its
+// share of the two halo rows (n0 - 1 and n0 + ROWS) of one image.
+template <int L, typename C>
+__device__ __forceinline__ void load_own(int N, size_t fo, int n, int t, const C* __restrict__ src,
+                                         C (&dst)[RowCfg<L>::EPT]) {
+#pragma unroll
+  for (int e = 0; e < RowCfg<L>::EPT; ++e) {
+    const int m = t + e * RowCfg<L>::TT;
+    dst[e] = src[(n < N && m < N) ? fo + (size_t)n * N + m : 0];
+  }
+}
+template <int L, typename C>
+__device__ __forceinline__ void load_halo2(int N, size_t fo, int n0, const C* __restrict__ src,
+                                           C (&dst)[RowCfg<L>::HX2]) {
+  constexpr int ROWS = RowCfg<L>::ROWS, W = RowCfg<L>::W;
+#pragma unroll
+  for (int s = 0; s < RowCfg<L>::HX2; ++s) {
+    const int j = threadIdx.x + s * 256;
+    const int sel = j / W, m = j % W;  // sel 0: n0-1, 1: n0+ROWS
+    const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+    const bool ok = j < 2 * W && m < N && img >= 0 && img < N;
+    dst[s] = src[ok ? fo + (size_t)img * N + m : 0];
+  }
+}
+
 template <int L, int PHI, typename C>
 __global__ __launch_bounds__(256) void k_update(
     int N, const C* __restrict__ T, const C* __restrict__ x_old, C* __restrict__ x_new,
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(256) void k_update(
   constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
   constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L, C>();
-  constexpr int HX = (2 * W + 255) / 256;  // halo elements per thread (2 rows, j -> j/W, j%W)
+  constexpr int HX = RC::HX2;  // halo elements per thread (2 rows, j -> j/W, j%W)
   // SEP: the x tile and the transform buffers are separate, and the x work
   // runs before the inverse transform (the halo and old-x registers are free
   // by then): the FP64 form at L <= 512, where registers bound occupancy.
@@ -275,25 +301,18 @@ __global__ __launch_bounds__(256) void k_update(
 #pragma unroll
     for (int e = 0; e < FftShape<L>::V; ++e) val[e] = row[t + e * TT];
   }
+  // LATE (FP64 at L = 1024, 16 transform values per thread): each image is
+  // loaded just before its first use, after the inverse transform, so that
+  // few of them are live at once (registers bound this form).
+  constexpr bool LATE = sizeof(C) == 16 && L >= 1024;
   C xo[EPT], dv[EPT], ro[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int m = t + e * TT;
-    const size_t idx = (n < N && m < N) ? fo + (size_t)n * N + m : 0;
-    xo[e] = x_old[idx];
-    dv[e] = d[idx];
-    ro[e] = r[idx];
-  }
   C hx[HX], hd[HX];
-#pragma unroll
-  for (int s = 0; s < HX; ++s) {
-    const int j = threadIdx.x + s * 256;
-    const int sel = j / W, m = j % W;  // sel 0: n0-1, 1: n0+ROWS
-    const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
-    const bool ok = j < 2 * W && m < N && img >= 0 && img < N;
-    const size_t idx = ok ? fo + (size_t)img * N + m : 0;
-    hx[s] = x_old[idx];
-    hd[s] = d[idx];
+  if constexpr (!LATE) {
+    load_own<L>(N, fo, n, t, x_old, xo);
+    load_own<L>(N, fo, n, t, d, dv);
+    load_own<L>(N, fo, n, t, r, ro);
+    load_halo2<L>(N, fo, n0, x_old, hx);
+    load_halo2<L>(N, fo, n0, d, hd);
   }
   load_twiddles<L>(tw, twg);
 
@@ -315,6 +334,10 @@ __global__ __launch_bounds__(256) void k_update(
     fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
     __syncthreads();  // the transform buffers become the x tile
   }
+  if constexpr (LATE) {
+    load_own<L>(N, fo, n, t, x_old, xo);
+    load_halo2<L>(N, fo, n0, x_old, hx);
+  }
 
   // Old x: tile, divergence and gradient at the start of the iteration.
 #pragma unroll
@@ -331,6 +354,8 @@ __global__ __launch_bounds__(256) void k_update(
   }
   __syncthreads();  // x tile, twiddles, step length
   const R af = salpha;
+  // go: the old gradient (LATE: the old divergence; the gradient is formed
+  // in the last loop, with the same operations)
   C go[EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -340,29 +365,41 @@ __global__ __launch_bounds__(256) void k_update(
       const C* mo = Xt + (team + 1) * N;
       const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
                                       n + 1 < N ? mo + N : nullptr, m, N, delta);
-      go[e] = grad_from(ro[e], div_o, lam);
+      if constexpr (LATE) go[e] = div_o;
+      else go[e] = grad_from(ro[e], div_o, lam);
     }
   }
   __syncthreads();  // every read of the old x is done
 
-  // New x = x + alpha d, in place (each thread rewrites the entries it wrote).
+  // New x = x + alpha d, in place (each thread rewrites the entries it wrote;
+  // LATE reads its old values back from the tile).
+  if constexpr (LATE) {
+    load_own<L>(N, fo, n, t, d, dv);
+    load_halo2<L>(N, fo, n0, d, hd);
+  }
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int m = t + e * TT;
-    if (n < N && m < N) Xt[(team + 1) * N + m] = c_axpy(af, dv[e], xo[e]);
+    if (n < N && m < N) {
+      C* p = Xt + (team + 1) * N + m;
+      *p = c_axpy(af, dv[e], LATE ? *p : xo[e]);
+    }
   }
 #pragma unroll
   for (int s = 0; s < HX; ++s) {
     const int j = threadIdx.x + s * 256;
     const int sel = j / W, m = j % W;
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
-    if (j < 2 * W && m < N && img >= 0 && img < N)
-      Xt[(img - n0 + 1) * N + m] = c_axpy(af, hd[s], hx[s]);
+    if (j < 2 * W && m < N && img >= 0 && img < N) {
+      C* p = Xt + (img - n0 + 1) * N + m;
+      *p = c_axpy(af, hd[s], LATE ? *p : hx[s]);
+    }
   }
 
   // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
   if constexpr (SEP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
   __syncthreads();  // new x tile complete
+  if constexpr (LATE) load_own<L>(N, fo, n, t, r, ro);
 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -373,15 +410,16 @@ __global__ __launch_bounds__(256) void k_update(
       const C* mn = Xt + (team + 1) * N;
       const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
                                       n + 1 < N ? mn + N : nullptr, m, N, delta);
+      const C goe = LATE ? grad_from(ro[e], go[e], lam) : go[e];
       const C rn = c_axpy(af, val[e], ro[e]);
       const C gn = grad_from(rn, div_n, lam);
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
       acc[0] += gx * gx + gy * gy;
-      acc[1] += gx * (double)go[e].x + gy * (double)go[e].y;
+      acc[1] += gx * (double)goe.x + gy * (double)goe.y;
       acc[2] += gx * (double)dv[e].x + gy * (double)dv[e].y;
-      acc[3] += (double)go[e].x * (double)go[e].x + (double)go[e].y * (double)go[e].y;
+      acc[3] += (double)goe.x * (double)goe.x + (double)goe.y * (double)goe.y;
     }
   }
   block_sum<4>(acc, red);
