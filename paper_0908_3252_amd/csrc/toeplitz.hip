@@ -64,9 +64,12 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
 template <int L, int ES = 1>
 struct ColCfg {
   static constexpr int T = FftShape<L>::T;
-  static constexpr int THREADS = (L == 512 && ES == 1) ? 512 : 256;
+  static constexpr int THREADS = ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
-  static constexpr int COLS = ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
+  // (FP64 at L >= 1024 keeps 8 columns: 128-byte row segments, whole cache
+  // lines; that form is register-bound to one block per CU anyway)
+  static constexpr int COLS = (L >= 1024 && ES == 2) ? 8
+                              : ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
   static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
 };
 
