@@ -197,7 +197,11 @@ recon_status_t recon_solve(recon_plan_t plan, const float* y, int32_t B,
                            void* stream);
 
 /* Resumable form of recon_solve for the same workspace (used to inspect the
- * iteration state between iterations).
+ * iteration state between iterations), with the full criterion of Section
+ * 3.3: J(x) = ||y - A x||^2 + lambda sum phi(|D x|) + lambda0 sum
+ * phi_alpha0(|x|), the second sum being the background penalty Omega_0 with
+ * the Huber function of threshold alpha0 (lambda0 = 0 turns it off, as in
+ * recon_solve; lambda0 >= 0, and alpha0 > 0 when lambda0 > 0).
  *   recon_solve_begin: b = A^H y (or b given: y == NULL and b_in != NULL),
  *                      initial state from x0 (x0 == NULL means zeros);
  *   recon_solve_iterate: run `iters` more iterations;
@@ -207,8 +211,9 @@ recon_status_t recon_solve(recon_plan_t plan, const float* y, int32_t B,
  * 3 = d (search direction for the next iteration), 4 = b. */
 recon_status_t recon_solve_begin(recon_plan_t plan, const float* y,
                                  const float* b_in, int32_t B, double lambda,
-                                 double delta, int32_t phi, const float* x0,
-                                 void* ws, size_t ws_bytes, void* stream);
+                                 double delta, double lambda0, double alpha0,
+                                 int32_t phi, const float* x0, void* ws,
+                                 size_t ws_bytes, void* stream);
 recon_status_t recon_solve_iterate(recon_plan_t plan, int32_t iters, void* ws,
                                    size_t ws_bytes, void* stream);
 recon_status_t recon_solve_end(recon_plan_t plan, float* x_out,
@@ -232,8 +237,10 @@ recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
  *   recon_pool_admit:  start a frame in an idle (or retired) slot: ||y||^2,
  *                      b = A^H y and the initial state, with a budget of
  *                      `iters` iterations from the pool's current iteration
- *                      counter.  y: device complex64 [M] (the plan's sample
- *                      order).  RECON_E_STATE if the slot is still running.
+ *                      counter, and its own lambda, delta, lambda0, alpha0
+ *                      (as recon_solve_begin).  y: device complex64 [M] (the
+ *                      plan's sample order).  RECON_E_STATE if the slot is
+ *                      still running.
  *   recon_pool_step:   run `iters` iterations of the pool (all running slots
  *                      advance; slots whose budget is used up stay frozen).
  *   recon_pool_retire: objective/stats of a finished slot (stats: device
@@ -249,8 +256,9 @@ recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
 recon_status_t recon_pool_reset(recon_plan_t plan, int32_t B, int32_t phi,
                                 void* ws, size_t ws_bytes, void* stream);
 recon_status_t recon_pool_admit(recon_plan_t plan, int32_t slot, const float* y,
-                                double lambda, double delta, int32_t iters,
-                                void* ws, size_t ws_bytes, void* stream);
+                                double lambda, double delta, double lambda0,
+                                double alpha0, int32_t iters, void* ws,
+                                size_t ws_bytes, void* stream);
 recon_status_t recon_pool_step(recon_plan_t plan, int32_t iters, void* ws,
                                size_t ws_bytes, void* stream);
 recon_status_t recon_pool_retire(recon_plan_t plan, int32_t slot, float* x_out,

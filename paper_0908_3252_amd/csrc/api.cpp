@@ -138,11 +138,11 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64) {
   w.nb1 = cdiv(N, w.rows);
   w.nb3 = L / fft_cols_per_block(L, f64);  // <d, Qd> partials come from the column pass
   w.nb4 = cdiv(N, w.rows);
-  w.p1 = take((size_t)B * w.nb1 * 2 * sizeof(double));
+  w.p1 = take((size_t)B * w.nb1 * 3 * sizeof(double));
   w.p3 = take((size_t)B * w.nb3 * sizeof(double));
   w.p4 = take((size_t)B * w.nb4 * 4 * sizeof(double));
   w.pg0 = take((size_t)B * w.nb4 * sizeof(double));
-  w.pobj = take((size_t)B * w.nb4 * 3 * sizeof(double));
+  w.pobj = take((size_t)B * w.nb4 * 4 * sizeof(double));
   w.params = take((size_t)B * sizeof(FrameParam));
   w.yy = take((size_t)B * sizeof(double));
   w.yyp = take((size_t)B * sumsq_parts() * sizeof(double));
@@ -478,9 +478,18 @@ recon_status_t recon_gram_apply(recon_plan_t p, const float* v, int32_t B, float
                     w.img(w.lay.T), nullptr, as_stream(stream));
 }
 
+// lambda0 >= 0 and, when it is > 0, alpha0 > 0 (the background term).
+static recon_status_t check_background(double lambda0, double alpha0) {
+  if (!(lambda0 >= 0.0) || !std::isfinite(lambda0)) return fail(RECON_E_RANGE, "lambda0 must be >= 0");
+  if (lambda0 > 0.0 && (!(alpha0 > 0.0) || !std::isfinite(alpha0)))
+    return fail(RECON_E_RANGE, "alpha0 must be > 0");
+  return RECON_OK;
+}
+
 recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
-                                 double lambda, double delta, int32_t phi, const float* x0,
-                                 void* ws, size_t ws_bytes, void* stream) {
+                                 double lambda, double delta, double lambda0, double alpha0,
+                                 int32_t phi, const float* x0, void* ws, size_t ws_bytes,
+                                 void* stream) {
   g_last_error.clear();
   if (!p) return fail(RECON_E_ARG, "NULL plan");
   if (!y && !b_in) return fail(RECON_E_ARG, "need y or b");
@@ -489,8 +498,10 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
   if (phi != RECON_PHI_QUADRATIC && (!(delta > 0.0) || !std::isfinite(delta)))
     return fail(RECON_E_RANGE, "delta must be > 0");
+  recon_status_t st = check_background(lambda0, alpha0);
+  if (st != RECON_OK) return st;
   Ws w;
-  recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  st = check_ws(p, ws, ws_bytes, B, &w);
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const int N = p->N;
@@ -513,7 +524,8 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
                              s));
     HIP_TRY(launch_zero_f64((size_t)B, yy, s));
   }
-  HIP_TRY(launch_set_params(B, lambda, delta, INT32_MAX, w.params(), s));
+  HIP_TRY(launch_set_params(B, lambda, delta, lambda0, lambda0 > 0.0 ? alpha0 : 1.0, INT32_MAX,
+                            w.params(), s));
   if (p->f64) {
     // x0 widened into the second iterate buffer (free before iteration 1)
     const double2* x0w = nullptr;
@@ -676,7 +688,7 @@ static recon_status_t stats_of(recon_plan_t p, const SolveCtx& c, const Ws& w, i
                                int xi, int iters, recon_stats_t* stats, hipStream_t s) {
   const int N = p->N;
   const size_t fo = (size_t)f0 * N * N;
-  double* pobj = w.dbl(w.lay.pobj) + (size_t)f0 * w.lay.nb4 * 3;
+  double* pobj = w.dbl(w.lay.pobj) + (size_t)f0 * w.lay.nb4 * 4;
   if (p->f64)
     HIP_TRY(launch_objective(c.phi, N, w.lay.rows, B, w.img64(w.lay.x[xi]) + fo,
                              w.img64(w.lay.b) + fo, w.img64(w.lay.r) + fo, pobj,
@@ -719,7 +731,7 @@ recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, double lam
                            size_t ws_bytes, recon_stats_t* stats, void* stream) {
   if (!p || !y || !x) return fail(RECON_E_ARG, "NULL argument");
   if (iters < 0) return fail(RECON_E_ARG, "iters must be >= 0");
-  recon_status_t st = recon_solve_begin(p, y, nullptr, B, lambda, delta, phi,
+  recon_status_t st = recon_solve_begin(p, y, nullptr, B, lambda, delta, 0.0, 1.0, phi,
                                         x_in_is_x0 ? x : nullptr, ws, ws_bytes, stream);
   if (st != RECON_OK) return st;
   st = recon_solve_iterate(p, iters, ws, ws_bytes, stream);
@@ -739,7 +751,7 @@ recon_status_t recon_pool_reset(recon_plan_t p, int32_t B, int32_t phi, void* ws
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
   if (st != RECON_OK) return st;
   // every slot idle: stop_at = 0
-  HIP_TRY(launch_set_params(B, 0.0, 1.0, 0, w.params(), as_stream(stream)));
+  HIP_TRY(launch_set_params(B, 0.0, 1.0, 0.0, 1.0, 0, w.params(), as_stream(stream)));
   std::lock_guard<std::mutex> lk(p->mu);
   SolveCtx& c = p->solves[ws];
   c = SolveCtx{};
@@ -760,8 +772,8 @@ static recon_status_t get_pool(recon_plan_t p, void* ws, SolveCtx* out) {
 }
 
 recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, double lambda,
-                                double delta, int32_t iters, void* ws, size_t ws_bytes,
-                                void* stream) {
+                                double delta, double lambda0, double alpha0, int32_t iters,
+                                void* ws, size_t ws_bytes, void* stream) {
   g_last_error.clear();
   if (!p || !y) return fail(RECON_E_ARG, "NULL argument");
   SolveCtx c;
@@ -773,6 +785,8 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, do
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
   if (c.phi != RECON_PHI_QUADRATIC && (!(delta > 0.0) || !std::isfinite(delta)))
     return fail(RECON_E_RANGE, "delta must be > 0");
+  st = check_background(lambda0, alpha0);
+  if (st != RECON_OK) return st;
   Ws w;
   st = check_ws(p, ws, ws_bytes, c.B, &w);
   if (st != RECON_OK) return st;
@@ -788,7 +802,8 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, do
                                reinterpret_cast<float*>(w.base + w.lay.sc) + slot, s);
   if (st != RECON_OK) return st;
   const int stop = k + iters;
-  HIP_TRY(launch_set_params(1, lambda, delta, stop, w.params() + slot, s));
+  HIP_TRY(launch_set_params(1, lambda, delta, lambda0, lambda0 > 0.0 ? alpha0 : 1.0, stop,
+                            w.params() + slot, s));
   double* p4 = w.dbl(w.lay.p4) + (size_t)slot * w.lay.nb4 * 4;
   double* pg0 = w.dbl(w.lay.pg0) + (size_t)slot * w.lay.nb4;
   if (p->f64)

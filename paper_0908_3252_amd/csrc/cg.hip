@@ -24,9 +24,10 @@ __global__ void k_zero_f64(size_t n, double* p) {
     p[i] = 0.0;
 }
 
-__global__ void k_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp) {
+__global__ void k_set_params(int B, double lam, double delta, double lam0, double alpha0,
+                             int stop_at, FrameParam* fp) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < B) fp[f] = FrameParam{lam, delta, stop_at, 0};
+  if (f < B) fp[f] = FrameParam{lam, delta, lam0, alpha0, stop_at, 0};
 }
 
 // Complex values widened to the FP64 iteration, or rounded back to FP32.
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(256) void k_init(
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
   const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
+  const R lam0 = (R)fp[f].lam0, alpha0 = (R)fp[f].alpha0;
   const int r_lo = max(n0 - 1, 0), r_hi = min(n0 + ROWS + 1, N);
   for (int i = threadIdx.x; i < (r_hi - r_lo) * N; i += 256) {
     const int rr = i / N, m = i - rr * N;
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(256) void k_init(
     const C bv = b[idx];
     const C q = qx0 ? qx0[idx] : cmk<C>(0, 0);
     const C rn = c_sub(q, bv);
-    const C gn = cmk<C>(rfma(lam, div.x, 2 * rn.x), rfma(lam, div.y, 2 * rn.y));
+    const C gn = grad_full(rn, div, mid[m], lam, lam0, alpha0);
     x[idx] = mid[m];
     r[idx] = rn;
     d[idx] = cmk<C>(0, 0);
@@ -92,20 +94,22 @@ __global__ __launch_bounds__(256) void k_init(
 }
 
 // Criterion J = ||y||^2 - 2 Re<x, b> + Re<x, Qx> + lam sum phi(|Dx|)
-// (Section 3.4, Eq. NewCritLS) with Qx = r + b:
-// partials [Re<x, b>, Re<x, r>, sum phi] per block.
+// + lam0 sum phi_alpha0(|x|) (Section 3.4, Eq. NewCritLS; the background term
+// of Section 3.3, Huber) with Qx = r + b:
+// partials [Re<x, b>, Re<x, r>, sum phi, sum phi_alpha0] per block.
 template <int PHI, typename C>
 __global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const C* __restrict__ x,
                                                    const C* __restrict__ b,
                                                    const C* __restrict__ r,
                                                    double* __restrict__ pobj,
                                                    const FrameParam* __restrict__ fp) {
-  __shared__ double red[3 * 4];
+  __shared__ double red[4 * 4];
   const int f = blockIdx.y;
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
-  const double delta = fp[f].delta;
-  double acc[3] = {0.0, 0.0, 0.0};
+  const double delta = fp[f].delta, alpha0 = fp[f].alpha0;
+  const bool bg = fp[f].lam0 != 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int own = min(ROWS, N - n0);
   for (int i = threadIdx.x; i < own * N; i += 256) {
     const int rr = i / N, m = i - rr * N;
@@ -114,6 +118,7 @@ __global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const C* __r
     const C xv = x[idx], bv = b[idx], rv = r[idx];
     acc[0] += (double)xv.x * bv.x + (double)xv.y * bv.y;
     acc[1] += (double)xv.x * rv.x + (double)xv.y * rv.y;
+    if (bg) acc[3] += pen_phi<1>((double)xv.x * xv.x + (double)xv.y * xv.y, alpha0);
     if (n + 1 < N) {
       const C xd = x[idx + N];
       const double tx = (double)xd.x - xv.x, ty = (double)xd.y - xv.y;
@@ -125,12 +130,13 @@ __global__ __launch_bounds__(256) void k_objective(int N, int ROWS, const C* __r
       acc[2] += pen_phi<PHI>(tx * tx + ty * ty, delta);
     }
   }
-  block_sum<3>(acc, red);
+  block_sum<4>(acc, red);
   if (threadIdx.x == 0) {
-    double* o = pobj + ((size_t)f * gridDim.x + blockIdx.x) * 3;
+    double* o = pobj + ((size_t)f * gridDim.x + blockIdx.x) * 4;
     o[0] = acc[0];
     o[1] = acc[1];
     o[2] = acc[2];
+    o[3] = acc[3];
   }
 }
 
@@ -147,13 +153,14 @@ __global__ void k_stats(int B, const double* __restrict__ pobj, int nbo,
   // one wavefront per frame
   const int f = blockIdx.x;
   if (f >= B) return;
-  const double xb = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 0, nbo, 3);
-  const double xr = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 1, nbo, 3);
-  const double ph = wave_sum_partials(pobj + (size_t)f * nbo * 3 + 2, nbo, 3);
+  const double xb = wave_sum_partials(pobj + (size_t)f * nbo * 4 + 0, nbo, 4);
+  const double xr = wave_sum_partials(pobj + (size_t)f * nbo * 4 + 1, nbo, 4);
+  const double ph = wave_sum_partials(pobj + (size_t)f * nbo * 4 + 2, nbo, 4);
+  const double ph0 = wave_sum_partials(pobj + (size_t)f * nbo * 4 + 3, nbo, 4);
   const double gg = wave_sum_partials(p4 + (size_t)f * nb4 * 4, nb4, 4);
   const double g0 = wave_sum_partials(pg0 + (size_t)f * nbg, nbg, 1);
   if (threadIdx.x == 0) {
-    const double J = yy[f] - xb + xr + (double)fp[f].lam * ph;
+    const double J = yy[f] - xb + xr + fp[f].lam * ph + fp[f].lam0 * ph0;
     StatsOut o;
     o.J = J;
     o.gnorm0 = sqrt(g0);
@@ -181,6 +188,7 @@ __global__ __launch_bounds__(256) void k_export(int N, int ROWS, const C* __rest
   const int n0 = blockIdx.x * ROWS;
   const size_t fo = (size_t)f * N * N;
   const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
+  const R lam0 = (R)fp[f].lam0, alpha0 = (R)fp[f].alpha0;
   R bf = 0;
   if (dir) {
     const double* pf = p4 + (size_t)f * nb4 * 4;
@@ -208,7 +216,7 @@ __global__ __launch_bounds__(256) void k_export(int N, int ROWS, const C* __rest
     const C div = divergence<PHI>(n > 0 ? mid - N : nullptr, mid,
                                   n + 1 < N ? mid + N : nullptr, m, N, delta);
     const C rv = r[idx];
-    const C g = cmk<C>(rfma(lam, div.x, 2 * rv.x), rfma(lam, div.y, 2 * rv.y));
+    const C g = grad_full(rv, div, mid[m], lam, lam0, alpha0);
     if (dir) {
       const C dv = d_old[idx];
       out[idx] = to_f32(cmk<C>(rfma(bf, dv.x, -g.x), rfma(bf, dv.y, -g.y)));
@@ -232,9 +240,9 @@ hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp,
-                             hipStream_t s) {
-  k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, stop_at, fp);
+hipError_t launch_set_params(int B, double lam, double delta, double lam0, double alpha0,
+                             int stop_at, FrameParam* fp, hipStream_t s) {
+  k_set_params<<<cdiv(B, 256), 256, 0, s>>>(B, lam, delta, lam0, alpha0, stop_at, fp);
   return hipGetLastError();
 }
 

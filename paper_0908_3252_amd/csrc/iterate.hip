@@ -50,12 +50,6 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& f) {
   f = logical / nbx;
 }
 
-// g = 2 r + lam * div, as every kernel forms it.
-template <typename C>
-__device__ __forceinline__ C grad_from(C r, C div, real_t<C> lam) {
-  return cmk<C>(rfma(lam, div.x, 2 * r.x), rfma(lam, div.y, 2 * r.y));
-}
-
 // ------------------------------------------------------- direction + rows
 template <int L, int PHI, typename C>
 __global__ __launch_bounds__(256) void k_dir_rowfft(
@@ -79,7 +73,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
   __shared__ C tw[L];
   __shared__ C sh[SH];
-  __shared__ double red[2 * 4];
+  __shared__ double red[3 * 4];
   __shared__ R sbeta;
   C* Xt = sh;  // tile row i <-> image row n0 - 1 + i (stride N)
   C* Dt = sh;  // after the gradients: tile row i <-> image row n0 + i
@@ -133,6 +127,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     if (threadIdx.x == 0) sbeta = (R)beta;
   }
   const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
+  const R lam0 = (R)fp[f].lam0, alpha0 = (R)fp[f].alpha0;
 
   // -- x tile
 #pragma unroll
@@ -151,7 +146,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   const R bf = sbeta;
 
   // -- gradient and new direction: own rows and the halo row n0 + ROWS
-  double gd = 0.0;
+  double gd = 0.0, cv0 = 0.0;
   C dn[EPT], dh[HD];
   R wdn[EPT], wrt[EPT];
 #pragma unroll
@@ -164,10 +159,12 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       const C div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
                                        n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
                                        wrt[e]);
-      const C g = grad_from(ro[e], div, lam);
+      const C g = grad_full(ro[e], div, xo[e], lam, lam0, alpha0);
       dn[e] = cmk<C>(rfma(bf, dv[e].x, -g.x), rfma(bf, dv[e].y, -g.y));
       d_new[fo + (size_t)n * N + m] = dn[e];
       gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
+      // background curvature w0(|x|) |d|^2 (majorant of Omega_0 along d)
+      cv0 += (double)bg_weight(xo[e], lam0, alpha0) * (double)c_abs2(dn[e]);
     }
   }
   if (n0 + ROWS < N) {
@@ -178,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       if (m < N) {
         const C* mid = Xt + (ROWS + 1) * N;
         const C div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
-        const C g = grad_from(hr[s], div, lam);
+        const C g = grad_full(hr[s], div, mid[m], lam, lam0, alpha0);
         dh[s] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
       }
     }
@@ -216,12 +213,13 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       }
     }
   }
-  double v2[2] = {gd, cv};
-  block_sum<2>(v2, red);  // ends with a block barrier: the tiles are free
+  double v3[3] = {gd, cv, cv0};
+  block_sum<3>(v3, red);  // ends with a block barrier: the tiles are free
   if (threadIdx.x == 0) {
-    double* o = p1 + ((size_t)f * gridDim.x + bx) * 2;
-    o[0] = v2[0];
-    o[1] = v2[1];
+    double* o = p1 + ((size_t)f * gridDim.x + bx) * 3;
+    o[0] = v3[0];
+    o[1] = v3[1];
+    o[2] = v3[2];
   }
 
   // -- row FFT of d (team layout in = own pixels)
@@ -319,12 +317,14 @@ __global__ __launch_bounds__(256) void k_update(
   // Step length: exact minimiser of the half-quadratic majorant along d
   // (one wavefront reduces, the block reads it after the barrier).
   const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
+  const R lam0 = (R)fp[f].lam0, alpha0 = (R)fp[f].alpha0;
   if (threadIdx.x < 64) {
-    const double* q1 = p1 + (size_t)f * nb1 * 2;
-    const double gd = wave_sum_partials(q1 + 0, nb1, 2);
-    const double cvv = wave_sum_partials(q1 + 1, nb1, 2);
+    const double* q1 = p1 + (size_t)f * nb1 * 3;
+    const double gd = wave_sum_partials(q1 + 0, nb1, 3);
+    const double cvv = wave_sum_partials(q1 + 1, nb1, 3);
+    const double cv0 = wave_sum_partials(q1 + 2, nb1, 3);
     const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
-    const double den = 2.0 * dqd + fp[f].lam * cvv;
+    const double den = 2.0 * dqd + fp[f].lam * cvv + fp[f].lam0 * cv0;
     const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
     if (threadIdx.x == 0) salpha = (R)alpha;
   }
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_update(
       const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
                                       n + 1 < N ? mo + N : nullptr, m, N, delta);
       if constexpr (LATE) go[e] = div_o;
-      else go[e] = grad_from(ro[e], div_o, lam);
+      else go[e] = grad_full(ro[e], div_o, xo[e], lam, lam0, alpha0);
     }
   }
   __syncthreads();  // every read of the old x is done
@@ -399,7 +399,10 @@ __global__ __launch_bounds__(256) void k_update(
   // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
   if constexpr (SEP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
   __syncthreads();  // new x tile complete
-  if constexpr (LATE) load_own<L>(N, fo, n, t, r, ro);
+  if constexpr (LATE) {
+    load_own<L>(N, fo, n, t, r, ro);
+    if (lam0 != 0) load_own<L>(N, fo, n, t, x_old, xo);  // the background term needs x
+  }
 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -410,9 +413,9 @@ __global__ __launch_bounds__(256) void k_update(
       const C* mn = Xt + (team + 1) * N;
       const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
                                       n + 1 < N ? mn + N : nullptr, m, N, delta);
-      const C goe = LATE ? grad_from(ro[e], go[e], lam) : go[e];
+      const C goe = LATE ? grad_full(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
       const C rn = c_axpy(af, val[e], ro[e]);
-      const C gn = grad_from(rn, div_n, lam);
+      const C gn = grad_full(rn, div_n, mn[m], lam, lam0, alpha0);
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;

@@ -14,8 +14,10 @@ constexpr int RECON_PREC_FP16X3 = 2;
 // part in iteration k of its workspace only while k < stop_at (slot pools of
 // the serving path; plain solves use INT32_MAX).
 struct FrameParam {
-  double lam;
-  double delta;
+  double lam;     // weight of the difference penalty Omega_1
+  double delta;   // its threshold
+  double lam0;    // weight of the background penalty Omega_0 (0: off)
+  double alpha0;  // its Huber threshold
   int32_t stop_at;
   int32_t pad;
 };
@@ -92,8 +94,8 @@ hipError_t launch_init(int phi, int N, int R, int B, const double2* b,
                        double2* r, double2* d, double* p4,
                        double* pg0, const FrameParam* fp, hipStream_t s);
 hipError_t launch_zero_f64(size_t n, double* p, hipStream_t s);
-hipError_t launch_set_params(int B, double lam, double delta, int stop_at, FrameParam* fp,
-                             hipStream_t s);
+hipError_t launch_set_params(int B, double lam, double delta, double lam0, double alpha0,
+                             int stop_at, FrameParam* fp, hipStream_t s);
 // n complex values widened to FP64 / rounded to FP32.
 hipError_t launch_widen(size_t n, const float2* in, double2* out, hipStream_t s);
 hipError_t launch_narrow(size_t n, const double2* in, float2* out, hipStream_t s);

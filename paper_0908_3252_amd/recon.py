@@ -61,12 +61,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_forward": (i32, [vp, vp, i32, vp, vp, sz, vp]),
         "recon_gram_apply": (i32, [vp, vp, i32, vp, vp, sz, vp]),
         "recon_solve": (i32, [vp, vp, i32, f64, f64, i32, i32, vp, i32, vp, sz, vp, vp]),
-        "recon_solve_begin": (i32, [vp, vp, vp, i32, f64, f64, i32, vp, vp, sz, vp]),
+        "recon_solve_begin": (i32, [vp, vp, vp, i32, f64, f64, f64, f64, i32, vp, vp, sz, vp]),
         "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
         "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
         "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
         "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
-        "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, i32, vp, sz, vp]),
+        "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, f64, f64, i32, vp, sz, vp]),
         "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
         "recon_pool_retire": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "recon_pool_iteration": (i64, [vp, vp]),
@@ -197,10 +197,16 @@ class Plan:
         return out
 
     def solve(self, y, lam: float, delta: float, iters: int, phi: str = "hyperbolic",
-              x0=None, want_stats: bool = True):
+              x0=None, want_stats: bool = True, lam0: float = 0.0, alpha0: float = 1.0):
+        """lam0 > 0 adds the background penalty lam0 sum phi_alpha0(|x|)
+        (Huber), through the resumable entry points."""
         import torch
         y = y.contiguous()
         B = y.shape[0]
+        if lam0:
+            self.begin(y=y, lam=lam, delta=delta, phi=phi, x0=x0, lam0=lam0, alpha0=alpha0)
+            self.iterate(iters)
+            return self.end() if want_stats else self.end()[0]
         x = (x0.clone().contiguous() if x0 is not None else
              torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda"))
         st = _dev_buf(B * STATS_DTYPE.itemsize) if want_stats else None
@@ -213,12 +219,14 @@ class Plan:
         return x, stats_to_numpy(st, B)
 
     # resumable form
-    def begin(self, y=None, b=None, B=None, lam=0.0, delta=1.0, phi="hyperbolic", x0=None):
+    def begin(self, y=None, b=None, B=None, lam=0.0, delta=1.0, phi="hyperbolic", x0=None,
+              lam0=0.0, alpha0=1.0):
         src = y if y is not None else b
         B = src.shape[0] if B is None else B
         ws, n = self.workspace(B)
         _check(load().recon_solve_begin(self._h, _ptr(y), _ptr(b), B, float(lam), float(delta),
-                                        PHI[phi], _ptr(x0), ws.data_ptr(), n, _stream()))
+                                        float(lam0), float(alpha0), PHI[phi], _ptr(x0),
+                                        ws.data_ptr(), n, _stream()))
         self._active_B = B
 
     def iterate(self, iters: int):
@@ -276,11 +284,12 @@ class Pool:
     def iteration(self) -> int:
         return int(load().recon_pool_iteration(self.plan.handle, self.ws.data_ptr()))
 
-    def admit(self, slot: int, y, lam: float, delta: float, iters: int):
+    def admit(self, slot: int, y, lam: float, delta: float, iters: int, lam0: float = 0.0,
+              alpha0: float = 1.0):
         """Start frame y (device complex64 [M]) in `slot` with `iters` iterations."""
         _check(load().recon_pool_admit(self.plan.handle, int(slot), y.data_ptr(), float(lam),
-                                       float(delta), int(iters), self.ws.data_ptr(), self.nbytes,
-                                       self._s()))
+                                       float(delta), float(lam0), float(alpha0), int(iters),
+                                       self.ws.data_ptr(), self.nbytes, self._s()))
 
     def step(self, iters: int):
         _check(load().recon_pool_step(self.plan.handle, int(iters), self.ws.data_ptr(),
