@@ -212,6 +212,7 @@ struct SolveCtx {
   int phi = 0;
   int iters = 0;                 // iterations run so far on this workspace (k)
   bool has_y = false;
+  bool bg = false;               // some frame has the background penalty on (lambda0 > 0)
   bool pool = false;             // slot pool of the serving path
   std::vector<int32_t> start_at;  // per slot (pool only): k at admission
   std::vector<int32_t> stop_at;   // per slot (pool only): k at which the slot stops
@@ -560,6 +561,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   c.phi = phi;
   c.iters = 0;
   c.has_y = y != nullptr;
+  c.bg = lambda0 > 0.0;
   return RECON_OK;
 }
 
@@ -591,7 +593,7 @@ static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const 
     {
       TraceScope ts(TK_DIR, s);
       HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, r, d_old, d_new, x_old, T, w.dbl(w.lay.p4),
-                                w.lay.nb4, w.dbl(w.lay.p1), w.params(), tw, k, s));
+                                w.lay.nb4, w.dbl(w.lay.p1), w.params(), tw, k, c.bg, s));
     }
     {
       TraceScope ts(TK_COL, s);
@@ -601,7 +603,7 @@ static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const 
       TraceScope ts(TK_UPDATE, s);
       HIP_TRY(launch_update(L, c.phi, N, B, T, x_old, x_new, d_new, r, w.dbl(w.lay.p1),
                             w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3, w.dbl(w.lay.p4), w.params(),
-                            tw, k, s));
+                            tw, k, c.bg, s));
     }
   }
   return RECON_OK;
@@ -817,6 +819,7 @@ recon_status_t recon_pool_admit(recon_plan_t p, int32_t slot, const float* y, do
   std::lock_guard<std::mutex> lk(p->mu);
   p->solves[ws].start_at[slot] = k;
   p->solves[ws].stop_at[slot] = stop;
+  if (lambda0 > 0.0) p->solves[ws].bg = true;  // until the pool is reset
   return RECON_OK;
 }
 

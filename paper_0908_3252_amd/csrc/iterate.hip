@@ -51,7 +51,7 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& f) {
 }
 
 // ------------------------------------------------------- direction + rows
-template <int L, int PHI, typename C>
+template <int L, int PHI, typename C, bool BG>
 __global__ __launch_bounds__(256) void k_dir_rowfft(
     int N, const C* __restrict__ r, const C* __restrict__ d_old, C* __restrict__ d_new,
     const C* __restrict__ x, C* __restrict__ T, const double* __restrict__ p4, int nb4,
@@ -159,12 +159,12 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       const C div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
                                        n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
                                        wrt[e]);
-      const C g = grad_full(ro[e], div, xo[e], lam, lam0, alpha0);
+      const C g = grad_full<BG>(ro[e], div, xo[e], lam, lam0, alpha0);
       dn[e] = cmk<C>(rfma(bf, dv[e].x, -g.x), rfma(bf, dv[e].y, -g.y));
       d_new[fo + (size_t)n * N + m] = dn[e];
       gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
       // background curvature w0(|x|) |d|^2 (majorant of Omega_0 along d)
-      cv0 += (double)bg_weight(xo[e], lam0, alpha0) * (double)c_abs2(dn[e]);
+      if constexpr (BG) cv0 += (double)bg_weight(xo[e], lam0, alpha0) * (double)c_abs2(dn[e]);
     }
   }
   if (n0 + ROWS < N) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       if (m < N) {
         const C* mid = Xt + (ROWS + 1) * N;
         const C div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
-        const C g = grad_full(hr[s], div, mid[m], lam, lam0, alpha0);
+        const C g = grad_full<BG>(hr[s], div, mid[m], lam, lam0, alpha0);
         dh[s] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
       }
     }
@@ -260,7 +260,7 @@ __device__ __forceinline__ void load_halo2(int N, size_t fo, int n0, const C* __
   }
 }
 
-template <int L, int PHI, typename C>
+template <int L, int PHI, typename C, bool BG>
 __global__ __launch_bounds__(256) void k_update(
     int N, const C* __restrict__ T, const C* __restrict__ x_old, C* __restrict__ x_new,
     const C* __restrict__ d, C* __restrict__ r, const double* __restrict__ p1, int nb1,
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_update(
     const double cvv = wave_sum_partials(q1 + 1, nb1, 3);
     const double cv0 = wave_sum_partials(q1 + 2, nb1, 3);
     const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
-    const double den = 2.0 * dqd + fp[f].lam * cvv + fp[f].lam0 * cv0;
+    const double den = 2.0 * dqd + fp[f].lam * cvv + (BG ? fp[f].lam0 * cv0 : 0.0);
     const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
     if (threadIdx.x == 0) salpha = (R)alpha;
   }
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_update(
       const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
                                       n + 1 < N ? mo + N : nullptr, m, N, delta);
       if constexpr (LATE) go[e] = div_o;
-      else go[e] = grad_full(ro[e], div_o, xo[e], lam, lam0, alpha0);
+      else go[e] = grad_full<BG>(ro[e], div_o, xo[e], lam, lam0, alpha0);
     }
   }
   __syncthreads();  // every read of the old x is done
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_update(
   __syncthreads();  // new x tile complete
   if constexpr (LATE) {
     load_own<L>(N, fo, n, t, r, ro);
-    if (lam0 != 0) load_own<L>(N, fo, n, t, x_old, xo);  // the background term needs x
+    if (BG && lam0 != 0) load_own<L>(N, fo, n, t, x_old, xo);  // the background term needs x
   }
 
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -413,9 +413,9 @@ __global__ __launch_bounds__(256) void k_update(
       const C* mn = Xt + (team + 1) * N;
       const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
                                       n + 1 < N ? mn + N : nullptr, m, N, delta);
-      const C goe = LATE ? grad_full(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
+      const C goe = LATE ? grad_full<BG>(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
       const C rn = c_axpy(af, val[e], ro[e]);
-      const C gn = grad_full(rn, div_n, mn[m], lam, lam0, alpha0);
+      const C gn = grad_full<BG>(rn, div_n, mn[m], lam, lam0, alpha0);
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
@@ -458,16 +458,37 @@ __global__ __launch_bounds__(256) void k_update(
     default: return hipErrorInvalidValue;             \
   }
 
+template <typename C, bool BG>
+static hipError_t dir_rowfft_t(int L, int phi, int N, int B, const C* r, const C* d_old,
+                               C* d_new, const C* x, C* T, const double* p4, int nb4, double* p1,
+                               const FrameParam* fp, const C* tw, int k, hipStream_t s) {
+  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP, C, BG><<<grid, 256, 0, s>>>(
+                                                        N, r, d_old, d_new, x, T, p4, nb4, p1,
+                                                        fp, tw, k))));
+  return hipGetLastError();
+}
+
 template <typename C>
 static hipError_t dir_rowfft_any(int L, int phi, int N, int B, const C* r, const C* d_old,
                                  C* d_new, const C* x, C* T, const double* p4, int nb4, double* p1,
-                                 const FrameParam* fp, const C* tw, int k, hipStream_t s) {
+                                 const FrameParam* fp, const C* tw, int k, bool bg,
+                                 hipStream_t s) {
   if (N > L / 2) return hipErrorInvalidValue;
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  return bg ? dir_rowfft_t<C, true>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s)
+            : dir_rowfft_t<C, false>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k,
+                                     s);
+}
+
+template <typename C, bool BG>
+static hipError_t update_t(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
+                           const C* d, C* r, const double* p1, int nb1, const double* p3, int nb3,
+                           double* p4, const FrameParam* fp, const C* tw, int k, hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP, C><<<grid, 256, 0, s>>>(
-                                                        N, r, d_old, d_new, x, T, p4, nb4, p1,
-                                                        fp, tw, k))));
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C, BG><<<grid, 256, 0, s>>>(
+                                                        N, T, x_old, x_new, d, r, p1, nb1, p3,
+                                                        nb3, p4, fp, tw, k))));
   return hipGetLastError();
 }
 
@@ -475,40 +496,39 @@ template <typename C>
 static hipError_t update_any(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
                              const C* d, C* r, const double* p1, int nb1, const double* p3,
                              int nb3, double* p4, const FrameParam* fp, const C* tw, int k,
-                             hipStream_t s) {
+                             bool bg, hipStream_t s) {
   if (N > L / 2) return hipErrorInvalidValue;
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
-  dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C><<<grid, 256, 0, s>>>(
-                                                        N, T, x_old, x_new, d, r, p1, nb1, p3,
-                                                        nb3, p4, fp, tw, k))));
-  return hipGetLastError();
+  return bg ? update_t<C, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw,
+                                k, s)
+            : update_t<C, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp,
+                                 tw, k, s);
 }
 
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, int k, hipStream_t s) {
-  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s);
+                             const float2* tw, int k, bool bg, hipStream_t s) {
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, s);
 }
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
                              const double2* d_old, double2* d_new, const double2* x, double2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const double2* tw, int k, hipStream_t s) {
-  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s);
+                             const double2* tw, int k, bool bg, hipStream_t s) {
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, s);
 }
 
 hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const float2* tw, int k, hipStream_t s) {
-  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, s);
+                         const float2* tw, int k, bool bg, hipStream_t s) {
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, s);
 }
 hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
                          double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const double2* tw, int k, hipStream_t s) {
-  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, s);
+                         const double2* tw, int k, bool bg, hipStream_t s) {
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, s);
 }
 
 }  // namespace recon

@@ -66,23 +66,24 @@ hipError_t launch_rowifft(int L, int N, int B, const double2* T, double2* out,
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, int k, hipStream_t s);
+                             const float2* tw, int k, bool bg, hipStream_t s);
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
                              const double2* d_old, double2* d_new, const double2* x, double2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const double2* tw, int k, hipStream_t s);
+                             const double2* tw, int k, bool bg, hipStream_t s);
 // Row inverse pass of the Gram apply fused with the update: Qd = rows of
 // IFFT(T) cropped; alpha from the partials; x_new = x + alpha d,
 // r += alpha Qd; partials for beta from g_old (recomputed from r, x) and
-// g_new = 2 r + grad R(x_new).
+// g_new = 2 r + grad R(x_new).  bg: some frame of the launch has the
+// background penalty on (lam0 > 0); without it the term is compiled out.
 hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const float2* tw, int k, hipStream_t s);
+                         const float2* tw, int k, bool bg, hipStream_t s);
 hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
                          double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const double2* tw, int k, hipStream_t s);
+                         const double2* tw, int k, bool bg, hipStream_t s);
 // Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), d = 0; partials
 // such that the first direction is -g, g = 2r + grad R(x0).  R rows per block.
 hipError_t launch_init(int phi, int N, int R, int B, const float2* b,

@@ -95,21 +95,25 @@ __device__ __forceinline__ C divergence(const C* up, const C* mid, const C* dn, 
 // term of Section 3.3 (Omega_0 = sum phi_alpha0(|x|), Huber) is on when
 // lam0 != 0.  Every kernel forms the gradient through this one function, so
 // every copy of it is bitwise the same.
-template <typename C>
+// BG = false compiles the term out (launches where no frame uses it).
+template <bool BG = true, typename C>
 __device__ __forceinline__ C grad_full(C r, C div, C x, real_t<C> lam, real_t<C> lam0,
                                        real_t<C> alpha0) {
   C g = cmk<C>(rfma(lam, div.x, 2 * r.x), rfma(lam, div.y, 2 * r.y));
-  if (lam0 != 0) {
-    const real_t<C> w = lam0 * pen_weight<1>(c_abs2(x), alpha0);
-    g = cmk<C>(rfma(w, x.x, g.x), rfma(w, x.y, g.y));
+  if constexpr (BG) {
+    if (lam0 != 0) {
+      const real_t<C> w = lam0 * pen_weight<1>(c_abs2(x), alpha0);
+      g = cmk<C>(rfma(w, x.x, g.x), rfma(w, x.y, g.y));
+    }
   }
   return g;
 }
 
 // Weight of the background term at one pixel (0 when it is off).
-template <typename C>
+template <bool BG = true, typename C>
 __device__ __forceinline__ real_t<C> bg_weight(C x, real_t<C> lam0, real_t<C> alpha0) {
-  return lam0 != 0 ? pen_weight<1>(c_abs2(x), alpha0) : real_t<C>(0);
+  if constexpr (BG) return lam0 != 0 ? pen_weight<1>(c_abs2(x), alpha0) : real_t<C>(0);
+  else return real_t<C>(0);
 }
 
 }  // namespace recon
