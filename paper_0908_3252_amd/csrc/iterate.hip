@@ -37,17 +37,17 @@ struct RowCfg {
 };
 
 // Logical (row block, frame) of this workgroup.  Workgroups are dispatched
-// round-robin over the 8 XCDs (linear id w runs on XCD w % 8); each XCD is
-// given a contiguous range of logical tiles, so neighbouring row blocks of a
-// frame, which read each other's rows as stencil halos, share one L2.
+// round-robin over the 8 XCDs (linear id w runs on XCD w % 8).  The row blocks
+// of each frame are cut into 8 contiguous ranges, one per XCD: neighbouring
+// row blocks, which read each other's rows as stencil halos, mostly share an
+// L2, and every frame is spread over the whole chip, so that a launch in which
+// only some frames are active (a partly filled serving pool) still keeps every
+// XCD busy.  A frame whose row-block count is not a multiple of 8 keeps the
+// plain order, which rotates consecutive blocks over the XCDs.
 __device__ __forceinline__ void xcd_tile(int& bx, int& f) {
-  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
-  const int w = blockIdx.x + blockIdx.y * nbx;
-  const int per = total / 8, rem = total % 8;
-  const int x = w % 8, i = w / 8;
-  const int logical = x * per + (x < rem ? x : rem) + i;
-  bx = logical % nbx;
-  f = logical / nbx;
+  const int nbx = gridDim.x;
+  f = blockIdx.y;
+  bx = (nbx % 8 == 0) ? (blockIdx.x % 8) * (nbx / 8) + blockIdx.x / 8 : blockIdx.x;
 }
 
 // ------------------------------------------------------- direction + rows
