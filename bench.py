@@ -207,8 +207,9 @@ def main():
                          "fp64i: that adjoint and the iteration in FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=10)
-    ap.add_argument("--serve-rate", type=float, default=250.0,
-                    help="served 256^2 request stream: Poisson arrivals per second (0: off)")
+    ap.add_argument("--serve-rate", default="250,450",
+                    help="served 256^2 request streams: comma list of Poisson arrival rates "
+                         "per second (0: off)")
     ap.add_argument("--serve-count", type=int, default=600)
     ap.add_argument("--criterion", default="plain", choices=["plain", "full"],
                     help="plain: hyperbolic difference penalty (the workload's criterion); "
@@ -365,25 +366,25 @@ def main():
             lat.append(time.perf_counter() - t0)
     # served stream of 256^2 requests (continuous batching): the benchmark's
     # frames arriving one by one (Poisson), each with its own 300 iterations
-    served = None
-    if args.serve_rate > 0 and args.workload == "series256" and args.criterion == "plain":
+    served = []
+    rates = [float(v) for v in str(args.serve_rate).split(",") if float(v) > 0]
+    if rates and args.workload == "series256" and args.criterion == "plain":
         from paper_0908_3252_amd import serving as srv
         arr = np.cumsum(np.random.default_rng([4, 256]).exponential(1.0, size=args.serve_count))
         key = (N, 16)
         base = [dict(id=i, arrival=float(arr[i]), key=key, y=y[i % B], lam=c_lam, delta=c_delta,
                      iters=iters) for i in range(args.serve_count)]
-        log(f"serving {args.serve_count} requests at {args.serve_rate}/s")
-        res = srv.serve(args.serve_rate, (base, {key: (k_host, N, L)}, {key: plan}),
-                        prec=args.prec, verify=1)
-        served = {"offered_per_sec": args.serve_rate, "requests": args.serve_count,
-                  "completed": res.get("completed", 0),
-                  "recons_per_sec": round(res.get("recons_per_sec", 0.0), 2),
-                  "p50_ms": round(res.get("p50_ms", float("nan")), 2),
-                  "p99_ms": round(res.get("p99_ms", float("nan")), 2),
-                  "status_ok": res["status_ok"],
-                  "bitwise_equal_standalone": res.get("bitwise_equal_standalone"),
-                  "what": "latency from arrival to result of single 256^2 reconstructions "
-                          "served by continuous batching (first 10% excluded)"}
+        for rate in rates:
+            log(f"serving {args.serve_count} requests at {rate}/s")
+            res = srv.serve(rate, (base, {key: (k_host, N, L)}, {key: plan}),
+                            prec=args.prec, verify=1)
+            served.append({"offered_per_sec": rate, "requests": args.serve_count,
+                           "completed": res.get("completed", 0),
+                           "recons_per_sec": round(res.get("recons_per_sec", 0.0), 2),
+                           "p50_ms": round(res.get("p50_ms", float("nan")), 2),
+                           "p99_ms": round(res.get("p99_ms", float("nan")), 2),
+                           "status_ok": res["status_ok"],
+                           "bitwise_equal_standalone": res.get("bitwise_equal_standalone")})
     crit = (f"hyperbolic delta={c_delta}, lambda={c_lam}" if args.criterion == "plain" else
             f"Huber differences alpha1={c_delta} lambda1={c_lam} + Huber background "
             f"alpha0={c_alpha0} lambda0={c_lam0}")
@@ -420,7 +421,10 @@ def main():
         "latency_ms": {"p50": round(1e3 * float(np.percentile(times, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(times, 99)), 3),
                        "what": f"one step = {B} reconstructions finishing together"},
-        "served_latency_256": served,
+        "served_latency_256": {
+            "what": "arrival-to-result latency of single 256^2 reconstructions (the frames "
+                    "above, 300 iterations each) served by continuous batching, first 10% "
+                    "excluded", "runs": served} if served else None,
         "single_frame_latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                     "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "roofline": roofline,

@@ -141,13 +141,18 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
       const int p = t + e * S::T;
       val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
+    // the column's kernel values are loaded before the transform, so that
+    // their latency is hidden behind it
+    const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
+    R kvv[S::V];
+#pragma unroll
+    for (int e = 0; e < S::V; ++e) kvv[e] = kq[t + e * S::T];
     // (INCOL: the reads above precede the exchange writes within the wave)
     fft_team<L, false, true>(val, t, INCOL ? tile + c * TS : tb, tw);
-    const R* kq = khat_s + (size_t)(q0 + (active ? c : 0)) * L;
     R acc = 0;
 #pragma unroll
     for (int e = 0; e < S::V; ++e) {
-      const R kv = kq[t + e * S::T];
+      const R kv = kvv[e];
       acc = rfma(kv, c_abs2(val[e]), acc);
       val[e] = c_scale(val[e], kv);
     }
