@@ -149,10 +149,15 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64) {
   w.sc = take((size_t)B * sizeof(float));
   w.adj_splits = adjoint_splits(M, N);
   {
-    const int g = adjoint_group(M, N);
-    const int frames = g < B ? g : B;
-    // FP64 complex partials serve both adjoint precisions
-    w.adj = take(w.adj_splits > 1 ? (size_t)w.adj_splits * frames * N * N * sizeof(double2) : 0);
+    // FP64 complex split-K partials serve every adjoint precision; the FP64
+    // adjoint has a launch shape of its own: room for the larger of the two
+    auto part_frames = [B](int splits, int group) -> size_t {
+      const int frames = group < B ? group : B;
+      return splits > 1 ? (size_t)splits * frames : 0;
+    };
+    const size_t a32 = part_frames(w.adj_splits, adjoint_group(M, N));
+    const size_t a64 = part_frames(adjoint64_splits(M, N), adjoint64_group(M, N));
+    w.adj = take((a32 > a64 ? a32 : a64) * N * N * sizeof(double2));
   }
   w.total = off;
   return w;

@@ -129,6 +129,9 @@ hipError_t launch_tables_f32(int64_t M, int N, const double* k, float2* ex,
 // Split-K over `splits` sample ranges into part[s][f][n][m] when splits > 1.
 int adjoint_splits(int64_t M, int N);
 int adjoint_group(int64_t M, int N);
+// split-K count and frames per launch of the FP64 adjoint (its own shape)
+int adjoint64_splits(int64_t M, int N);
+int adjoint64_group(int64_t M, int N);
 hipError_t launch_adjoint_f32(int64_t M, int N, int B, const float2* ex,
                               const float2* ey, const float2* y, float2* b,
                               float2* part, hipStream_t s);

@@ -203,17 +203,70 @@ __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __re
   }
 }
 
+// Launch shape of this adjoint: split-K count and frames per launch, chosen
+// so that a launch (tiles x splits x frames blocks) fills whole waves of
+// resident blocks.  The kernel holds 3 blocks per CU (register-bound), 768
+// on the 256 CUs; a launch of 1024 blocks ran one full wave and then a third
+// of one with two thirds of the chip idle.  Among shapes of equal wave
+// efficiency the one that also fills the chip for a single frame (a served
+// request) and then the one with the fewest blocks is taken; each split keeps
+// at least 8 stages of AK samples.  Depends on (M, N) only, so every frame's
+// sums are taken in the same order whatever the batch.
+constexpr int ADJ64_RESIDENT = 3 * 256;
+
+static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
+  const int64_t tiles = (int64_t)cdiv(N, AT) * cdiv(N, AT);
+  int64_t max_sp = (M + 8 * AK - 1) / (8 * AK);
+  if (max_sp > 192) max_sp = 192;
+  if (max_sp < 1) max_sp = 1;
+  auto eff = [](int64_t blocks) {
+    const int64_t waves = (blocks + ADJ64_RESIDENT - 1) / ADJ64_RESIDENT;
+    // efficiency in percent, rounded down
+    return (int)(100 * blocks / (waves * ADJ64_RESIDENT));
+  };
+  int best_sp = 1, best_g = 1, best_e = -1, best_e1 = -1;
+  int64_t best_blocks = 0;
+  for (int g = 1; g <= 16; ++g)
+    for (int64_t sp = 1; sp <= max_sp; ++sp) {
+      const int64_t blocks = tiles * sp * g;
+      const int e = eff(blocks), e1 = eff(tiles * sp);
+      const bool better = e > best_e || (e == best_e && e1 > best_e1) ||
+                          (e == best_e && e1 == best_e1 && blocks < best_blocks);
+      if (better) {
+        best_e = e;
+        best_e1 = e1;
+        best_blocks = blocks;
+        best_sp = (int)sp;
+        best_g = g;
+      }
+    }
+  *splits = best_sp;
+  *group = best_g;
+}
+
+int adjoint64_splits(int64_t M, int N) {
+  int sp, g;
+  adjoint64_shape(M, N, &sp, &g);
+  return sp;
+}
+
+int adjoint64_group(int64_t M, int N) {
+  int sp, g;
+  adjoint64_shape(M, N, &sp, &g);
+  return sp == 1 ? (1 << 30) : g;
+}
+
 template <typename O>
 static hipError_t adjoint_f64_any(int64_t M, int N, int B, const double2* ph, const float2* y,
                                   O* b, double2* part, hipStream_t s) {
-  const int sp = adjoint_splits(M, N);
+  const int sp = adjoint64_splits(M, N);
   const int R = phase_record(N);
   if (sp == 1) {
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * B, 1);
     k_adjoint_f64<O><<<grid, 256, 0, s>>>(M, N, B, 1, ph, R, y, nullptr, b, 1.0 / (double)N);
     return hipGetLastError();
   }
-  const int G = adjoint_group(M, N);
+  const int G = adjoint64_group(M, N);
   for (int f0 = 0; f0 < B; f0 += G) {
     const int g = (B - f0 < G) ? B - f0 : G;
     dim3 grid(cdiv(N, AT), cdiv(N, AT) * g, sp);
