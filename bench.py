@@ -211,6 +211,8 @@ def main():
                     help="served 256^2 request streams: comma list of Poisson arrival rates "
                          "per second (0: off)")
     ap.add_argument("--serve-count", type=int, default=600)
+    ap.add_argument("--serve-chunk", type=int, default=10,
+                    help="iterations a served pool runs per scheduling step")
     ap.add_argument("--criterion", default="plain", choices=["plain", "full"],
                     help="plain: hyperbolic difference penalty (the workload's criterion); "
                          "full: the paper's criterion, Huber differences + background penalty")
@@ -377,13 +379,13 @@ def main():
         for rate in rates:
             log(f"serving {args.serve_count} requests at {rate}/s")
             res = srv.serve(rate, (base, {key: (k_host, N, L)}, {key: plan}),
-                            prec=args.prec, verify=1)
+                            prec=args.prec, verify=1, chunk=args.serve_chunk)
             served.append({"offered_per_sec": rate, "requests": args.serve_count,
                            "completed": res.get("completed", 0),
                            "recons_per_sec": round(res.get("recons_per_sec", 0.0), 2),
                            "p50_ms": round(res.get("p50_ms", float("nan")), 2),
                            "p99_ms": round(res.get("p99_ms", float("nan")), 2),
-                           "status_ok": res["status_ok"],
+                           "chunk": args.serve_chunk, "status_ok": res["status_ok"],
                            "bitwise_equal_standalone": res.get("bitwise_equal_standalone")})
     crit = (f"hyperbolic delta={c_delta}, lambda={c_lam}" if args.criterion == "plain" else
             f"Huber differences alpha1={c_delta} lambda1={c_lam} + Huber background "

@@ -210,8 +210,10 @@ __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __re
 // of one with two thirds of the chip idle.  Among shapes of equal wave
 // efficiency the one that also fills the chip for a single frame (a served
 // request) and then the one with the fewest blocks is taken; each split keeps
-// at least 8 stages of AK samples.  Depends on (M, N) only, so every frame's
-// sums are taken in the same order whatever the batch.
+// at least 8 stages of AK samples and the split-K partials of a launch stay
+// within 64 MiB (splits x frames x N^2 complex128 values <= 4 Mi).  Depends
+// on (M, N) only, so every frame's sums are taken in the same order whatever
+// the batch.
 constexpr int ADJ64_RESIDENT = 3 * 256;
 
 static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
@@ -226,8 +228,10 @@ static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
   };
   int best_sp = 1, best_g = 1, best_e = -1, best_e1 = -1;
   int64_t best_blocks = 0;
+  const int64_t max_part = (int64_t)1 << 22;  // complex128 partials per launch
   for (int g = 1; g <= 16; ++g)
     for (int64_t sp = 1; sp <= max_sp; ++sp) {
+      if (sp > 1 && sp * g * N * N > max_part) break;
       const int64_t blocks = tiles * sp * g;
       const int e = eff(blocks), e1 = eff(tiles * sp);
       const bool better = e > best_e || (e == best_e && e1 > best_e1) ||

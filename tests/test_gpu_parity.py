@@ -97,6 +97,27 @@ def test_adjoint_full_size_workload(prec):
     assert abs(float(yy.cpu()[0]) - yy_ref) < 1e-12 * yy_ref
 
 
+@pytest.mark.parametrize("N,karg,B", [
+    (128, (16, 2048, 2.0), 1),   # 192 sample splits, one frame per launch
+    (128, (8, 1024, 1.0), 4),    # 64 splits, 3 frames per launch: launches of 3 and 1
+    (192, (8, 2304, 2.0), 2),    # 85 splits (the last ones shorter), N not a power of two
+])
+def test_fp64_adjoint_launch_shapes(N, karg, B):
+    """The FP64 adjoint's launch shapes (split-K count and frames per launch
+    sized to whole waves of resident blocks) against the oracle's Eq.
+    AnnMatGD, every frame."""
+    rng = np.random.default_rng(N + B)
+    k = spiral(N, *karg)
+    plan = recon.Plan(k, N, prec=recon.FP64)
+    y = rand_c(rng, B, k.shape[0]).astype(np.complex64)
+    b = host(plan.adjoint(dev(y)))
+    b_ref = oracle.adjoint(y, k, N)
+    for f in range(B):
+        e = rel(b[f], b_ref[f])
+        print(f"N={N} M={k.shape[0]} frame {f}: adjoint rel {e:.2e}")
+        assert e < ADJ_TOL[recon.FP64]
+
+
 @pytest.mark.parametrize("N,L,karg", [(32, 64, (4, 256, 1.0)), (48, 128, (5, 199, 1.0)),
                                        (100, 256, (8, 313, 2.0)), (60, 256, (3, 500, 1.0))])
 def test_gram_kernel_and_spectrum(N, L, karg):
