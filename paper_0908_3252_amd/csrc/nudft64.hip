@@ -14,6 +14,10 @@
 // three unit steps: four complex products instead of sincospi evaluations
 // (on this chip FP64 vector work competes with the FP64 matrix pipe), with a
 // relative error of a few 1e-16.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -216,7 +220,7 @@ __global__ void k_split_reduce_f64(size_t count, int splits, const double2* __re
 // the batch.
 constexpr int ADJ64_RESIDENT = 3 * 256;
 
-static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
+static void adjoint64_shape_search(int64_t M, int N, int* splits, int* group) {
   const int64_t tiles = (int64_t)cdiv(N, AT) * cdiv(N, AT);
   int64_t max_sp = (M + 8 * AK - 1) / (8 * AK);
   if (max_sp > 192) max_sp = 192;
@@ -246,6 +250,26 @@ static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
     }
   *splits = best_sp;
   *group = best_g;
+}
+
+// The search above, remembered per (M, N): workspace layouts and launches
+// ask for the shape on every call.
+static void adjoint64_shape(int64_t M, int N, int* splits, int* group) {
+  static std::mutex mu;
+  static std::map<std::pair<int64_t, int>, std::pair<int, int>> memo;
+  const std::pair<int64_t, int> key(M, N);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) {
+      *splits = it->second.first;
+      *group = it->second.second;
+      return;
+    }
+  }
+  adjoint64_shape_search(M, N, splits, group);
+  std::lock_guard<std::mutex> lk(mu);
+  memo[key] = std::make_pair(*splits, *group);
 }
 
 int adjoint64_splits(int64_t M, int N) {
