@@ -211,6 +211,8 @@ def main():
                     help="served 256^2 request streams: comma list of Poisson arrival rates "
                          "per second (0: off)")
     ap.add_argument("--serve-count", type=int, default=600)
+    ap.add_argument("--no-phases", action="store_true",
+                    help="skip the separately timed phases (plan, adjoint, one apply, solve)")
     ap.add_argument("--serve-chunk", type=int, default=10,
                     help="iterations a served pool runs per scheduling step")
     ap.add_argument("--criterion", default="plain", choices=["plain", "full"],
@@ -366,6 +368,58 @@ def main():
         torch.cuda.synchronize()
         if i:
             lat.append(time.perf_counter() - t0)
+    # phases timed separately (events on the library's stream): plan + Gram
+    # kernel, batched adjoint, one batched Toeplitz apply (the public FP32
+    # apply, scored against the two-round-trip byte model), whole solve
+    phases = None
+    if not args.no_phases:
+        def time_phase(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(reps)]
+            for a, b_ in evs:
+                a.record()
+                fn()
+                b_.record()
+            torch.cuda.synchronize()
+            t = np.array([a.elapsed_time(b_) for a, b_ in evs])
+            return {"median_ms": round(float(np.median(t)), 4),
+                    "p10_ms": round(float(np.percentile(t, 10)), 4),
+                    "p90_ms": round(float(np.percentile(t, 90)), 4), "reps": reps}
+
+        def plan_gram():
+            h = ctypes.c_void_p()
+            recon._check(lib.recon_plan(k_host.ctypes.data, M, N, L, prec, plan.mem.data_ptr(),
+                                        plan_bytes, stream, ctypes.byref(h)))
+            recon._check(lib.recon_gram_kernel(h, gws.data_ptr(), gws_bytes, None, None, stream))
+            torch.cuda.current_stream().synchronize()
+            lib.recon_plan_destroy(h)
+
+        bq = torch.empty((B, N, N), dtype=torch.complex64, device="cuda")
+        vq = x.clone()
+        h0 = plan._h
+        log("timing phases")
+        ph_plan = time_phase(plan_gram, 5)
+        ph_adj = time_phase(lambda: recon._check(lib.recon_adjoint(
+            h0, y.data_ptr(), B, bq.data_ptr(), None, ws.data_ptr(), ws_bytes, stream)), 20)
+        ph_app = time_phase(lambda: recon._check(lib.recon_gram_apply(
+            h0, vq.data_ptr(), B, bq.data_ptr(), ws.data_ptr(), ws_bytes, stream)), 20)
+        ph_solve = time_phase(lambda: solve(h0, y.data_ptr(), B, x.data_ptr(), ws.data_ptr(),
+                                            ws_bytes, stats.data_ptr()), 5)
+        app_bytes = B * 80 * N * N + 16 * N * N  # per apply: 80 N^2 per frame + K-hat once
+        app_gbs = app_bytes / (ph_app["median_ms"] * 1e-3) / 1e9
+        ph_app.update({"model_bytes": app_bytes, "achieved_gbs": round(app_gbs, 1),
+                       "frac_of_hbm_peak": round(app_gbs / HBM_PEAK_GBS, 4),
+                       "what": "v -> Q v on complex64 frames: row FFTs, column pass, row "
+                               "inverse; bytes = v in + Qv out + the N x L intermediate "
+                               "written and read twice (80 N^2 per frame) + K-hat"})
+        ph_adj["achieved_tflops"] = round(8.0 * N * N * M * B / (ph_adj["median_ms"] * 1e-3)
+                                          / 1e12, 2)
+        phases = {"plan_and_gram_kernel": ph_plan, "adjoint_batch": ph_adj,
+                  "toeplitz_apply_batch": ph_app, "solve_batch": ph_solve, "frames": B}
+        del bq, vq
+
     # served stream of 256^2 requests (continuous batching): the benchmark's
     # frames arriving one by one (Poisson), each with its own 300 iterations
     served = []
@@ -423,6 +477,7 @@ def main():
         "latency_ms": {"p50": round(1e3 * float(np.percentile(times, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(times, 99)), 3),
                        "what": f"one step = {B} reconstructions finishing together"},
+        "phases": phases,
         "served_latency_256": {
             "what": "arrival-to-result latency of single 256^2 reconstructions (the frames "
                     "above, 300 iterations each) served by continuous batching, first 10% "

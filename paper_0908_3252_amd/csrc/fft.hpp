@@ -120,9 +120,57 @@ __device__ __forceinline__ void dft(C* a) {
   else dft8<INV, HALF>(a);
 }
 
-// One Stockham pass; returns the output positions of v[e] in pos[e].
-template <int L, int R, int NS, bool INV, bool HALF, typename C>
-__device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const C* tw,
+// Twiddles of one thread kept in registers (for V = 8, one butterfly per
+// radix-8 pass): the butterfly of pass P has a fixed k = t mod NS, and of its
+// seven twiddles W^{rk} the ones for r = 1, 2, 4 are loaded from the plan's
+// table g[i] = exp(-2 pi i i / L); r = 3, 5, 6, 7 are products of two of them
+// (W^3 = W W^2, W^5 = W W^4, W^6 = W^2 W^4, W^7 = W^3 W^4: at most two
+// roundings).  Loaded once, they serve every transform the thread runs.
+template <int L, typename C>
+struct TwRegs {
+  using S = FftShape<L>;
+  static_assert(S::V == 8, "one butterfly per radix-8 pass");
+  static constexpr int NPT = S::NP - 1;  // passes with twiddles (P >= 1)
+  C w[NPT > 0 ? NPT : 1][3];             // W^k, W^2k, W^4k
+  __device__ __forceinline__ void load(const C* __restrict__ g, int t) {
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+      const int ns = S::S0 << (3 * p);  // span of pass p + 1
+      const int k = t & (ns - 1);
+      const int st = k * (L / (8 * ns));
+      w[p][0] = g[st];
+      w[p][1] = g[2 * st];
+      w[p][2] = g[4 * st];
+    }
+  }
+};
+
+template <typename T>
+struct IsTwRegs {
+  static constexpr bool value = false;
+};
+template <int L, typename C>
+struct IsTwRegs<TwRegs<L, C>> {
+  static constexpr bool value = true;
+};
+
+// The seven twiddles W^{rk}, r = 1..7, of pass P from TwRegs.
+template <int P, int L, typename C>
+__device__ __forceinline__ void twiddles7(const TwRegs<L, C>& tw, C (&w)[7]) {
+  const C w1 = tw.w[P - 1][0], w2 = tw.w[P - 1][1], w4 = tw.w[P - 1][2];
+  w[0] = w1;
+  w[1] = w2;
+  w[2] = c_mul(w1, w2);
+  w[3] = w4;
+  w[4] = c_mul(w1, w4);
+  w[5] = c_mul(w2, w4);
+  w[6] = c_mul(w[2], w4);
+}
+
+// One Stockham pass (pass P, span NS); returns the output positions of v[e]
+// in pos[e].
+template <int L, int R, int NS, int P, bool INV, bool HALF, typename C, typename TW>
+__device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const TW& tw,
                                          int (&pos)[FftShape<L>::V]) {
   constexpr int NB = FftShape<L>::V / R;
   constexpr int T = FftShape<L>::T;
@@ -133,9 +181,18 @@ __device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const C*
     C a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
-    if constexpr (NS > 1) {
-      // Per-pass table: consecutive k are consecutive entries, so a wave's
-      // twiddle reads are conflict-free (or broadcasts when NS < 64).
+    if constexpr (NS > 1 && IsTwRegs<TW>::value) {
+      C w7[7];
+      twiddles7<P>(tw, w7);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = w7[r - 1];
+        if (INV) w.y = -w.y;
+        a[r] = c_mul(a[r], w);
+      }
+    } else if constexpr (NS > 1) {
+      // Per-pass LDS table: consecutive k are consecutive entries, so a
+      // wave's twiddle reads are conflict-free (or broadcasts when NS < 64).
       constexpr int OFF = NS - FftShape<L>::S0;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -224,13 +281,13 @@ __device__ __forceinline__ void fft_exchange(C (&v)[FftShape<L>::V],
   }
 }
 
-template <int L, bool INV, bool HALF_IN, int P, int NS, typename C>
-__device__ __forceinline__ void fft_passes(C (&v)[FftShape<L>::V], int t, C* tb, const C* tw) {
+template <int L, bool INV, bool HALF_IN, int P, int NS, typename C, typename TW>
+__device__ __forceinline__ void fft_passes(C (&v)[FftShape<L>::V], int t, C* tb, const TW& tw) {
   using S = FftShape<L>;
   constexpr int R = (P == 0 && S::REM) ? (1 << S::REM) : 8;
   constexpr bool HALF = HALF_IN && (P == 0);
   int pos[S::V];
-  fft_pass<L, R, NS, INV, HALF>(v, t, tw, pos);
+  fft_pass<L, R, NS, P, INV, HALF>(v, t, tw, pos);
   if constexpr (P + 1 < S::NP) {
     fft_exchange<L, P>(v, pos, t, tb);
     fft_passes<L, INV, HALF_IN, P + 1, NS * R>(v, t, tb, tw);
@@ -242,9 +299,10 @@ __device__ __forceinline__ void fft_passes(C (&v)[FftShape<L>::V], int t, C* tb,
 // Full transform.  For L > 512 every thread of the block must call this
 // (block barriers); for L <= 512 only the team's own wavefront is involved.
 // tb: this team's exchange buffers (fft_team_lds<L, C>() elements of LDS);
-// tw: the per-pass LDS twiddle table built by load_twiddles.
-template <int L, bool INV, bool HALF_IN, typename C>
-__device__ __forceinline__ void fft_team(C (&v)[FftShape<L>::V], int t, C* tb, const C* tw) {
+// tw: the per-pass LDS twiddle table built by load_twiddles (a pointer), or
+// the thread's TwRegs.
+template <int L, bool INV, bool HALF_IN, typename C, typename TW>
+__device__ __forceinline__ void fft_team(C (&v)[FftShape<L>::V], int t, C* tb, const TW& tw) {
   if (HALF_IN) {
 #pragma unroll
     for (int e = FftShape<L>::V / 2; e < FftShape<L>::V; ++e) v[e] = cmk<C>(0, 0);

@@ -98,7 +98,9 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   constexpr int TS = (INCOL && fft_team_lds<L, C>() > TS0)
                          ? (fft_team_lds<L, C>() + 15) / 16 * 16 + 2 : TS0;
   constexpr int NBUF = INCOL ? 1 : TEAMS * fft_team_lds<L, C>();
-  __shared__ C tw[L];
+  // FP32 at L <= 512: twiddles in registers (TwRegs) instead of an LDS table
+  constexpr bool TWR = sizeof(C) == 8 && L <= 512;
+  __shared__ C tw[TWR ? 1 : L];
   __shared__ C tile[COLS * TS];
   __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
@@ -116,7 +118,10 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     const int n = i / COLS, c = i - n * COLS;
     stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
   }
-  load_twiddles<L>(tw, twg);
+  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
+  TwRegs<(TWR ? L : 64), C> twr;
+  if constexpr (TWR) twr.load(twg, t);
+  else load_twiddles<L>(tw, twg);
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) {
     const int i = threadIdx.x + s * NT;
@@ -124,7 +129,6 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     if (n < N) tile[c * TS + n] = stg[s];
   }
   __syncthreads();
-  const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   C* tb = INCOL ? nullptr : team_buf<L>(bufs, team);
   // Wave-local teams touch only their own columns and buffers: no block
   // barrier inside the loop.  Multi-wave teams synchronise inside the FFT.
@@ -148,7 +152,8 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 #pragma unroll
     for (int e = 0; e < S::V; ++e) kvv[e] = kq[t + e * S::T];
     // (INCOL: the reads above precede the exchange writes within the wave)
-    fft_team<L, false, true>(val, t, INCOL ? tile + c * TS : tb, tw);
+    if constexpr (TWR) fft_team<L, false, true>(val, t, INCOL ? tile + c * TS : tb, twr);
+    else fft_team<L, false, true>(val, t, INCOL ? tile + c * TS : tb, tw);
     R acc = 0;
 #pragma unroll
     for (int e = 0; e < S::V; ++e) {
@@ -158,7 +163,8 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
     }
     if (active) dqd += (double)acc;
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
-    fft_team<L, true, false>(val, t, INCOL ? tile + c * TS : tb, tw);
+    if constexpr (TWR) fft_team<L, true, false>(val, t, INCOL ? tile + c * TS : tb, twr);
+    else fft_team<L, true, false>(val, t, INCOL ? tile + c * TS : tb, tw);
     if (active) {
 #pragma unroll
       for (int e = 0; e < S::V / 2; ++e) {
