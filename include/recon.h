@@ -158,6 +158,12 @@ recon_status_t recon_gram_kernel(recon_plan_t plan, void* ws, size_t ws_bytes,
 
 /* ---- operators ---------------------------------------------------------- */
 
+/* Batch limit: with a plan whose adjoint precision is RECON_FP32,
+ * RECON_BF16X3 or RECON_FP16X3, recon_adjoint, recon_forward, recon_solve
+ * and recon_solve_begin accept at most 64 frames per call (RECON_E_ARG
+ * above, before anything is launched); split larger batches into calls of
+ * <= 64 frames.  Plans with the FP64 adjoint have no such limit. */
+
 /* Appendix A.2, Eq. AnnMatGD: b[f] = A^H y[f], the paper's D
  * ("DFT of the data"), as an MFMA contraction over the M samples.
  * y: device complex64 [B][M]; b: device complex64 [B][N][N];

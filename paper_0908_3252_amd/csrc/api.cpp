@@ -265,6 +265,17 @@ struct Ws {
   FrameParam* params() const { return reinterpret_cast<FrameParam*>(base + lay.params); }
 };
 
+// Plans whose adjoint is FP32 or split-precision take at most this many
+// frames per adjoint, forward or solve call.
+constexpr int32_t MAX_BATCH_NON_FP64 = 64;
+
+recon_status_t check_batch(recon_plan_t p, int32_t B) {
+  if (p->prec != RECON_FP64 && B > MAX_BATCH_NON_FP64)
+    return fail(RECON_E_ARG, "plans with an FP32 or split-precision adjoint take at most 64 "
+                             "frames per adjoint, forward or solve call");
+  return RECON_OK;
+}
+
 recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws* out) {
   if (!ws) return fail(RECON_E_ARG, "workspace is NULL");
   if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
@@ -444,6 +455,7 @@ recon_status_t recon_adjoint(recon_plan_t p, const float* y, int32_t B, float* b
   if (!p || !y || !b) return fail(RECON_E_ARG, "NULL argument");
   Ws w;
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st == RECON_OK) st = check_batch(p, B);
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const float2* y2 = reinterpret_cast<const float2*>(y);
@@ -458,6 +470,7 @@ recon_status_t recon_forward(recon_plan_t p, const float* x, int32_t B, float* y
   if (!p || !x || !y) return fail(RECON_E_ARG, "NULL argument");
   Ws w;
   recon_status_t st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st == RECON_OK) st = check_batch(p, B);
   if (st != RECON_OK) return st;
   TraceScope ts(TK_FWD, as_stream(stream));
   if (p->has_tables())
@@ -508,6 +521,7 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   if (st != RECON_OK) return st;
   Ws w;
   st = check_ws(p, ws, ws_bytes, B, &w);
+  if (st == RECON_OK) st = check_batch(p, B);
   if (st != RECON_OK) return st;
   hipStream_t s = as_stream(stream);
   const int N = p->N;

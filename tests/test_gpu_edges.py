@@ -148,3 +148,39 @@ def test_largest_geometry():
     assert eq < 5e-6
     assert e < 1e-4
     assert st["status"][0] == 0
+
+
+@pytest.mark.parametrize("prec", [recon.FP32, recon.BF16X3, recon.FP16X3])
+def test_batch_limit_without_fp64_adjoint(prec):
+    """Plans with an FP32 or split-precision adjoint refuse more than 64 frames
+    per adjoint, forward or solve call, before launching anything.  (Larger
+    batches of these plans stay off the GPU: an unexplained fault at 128
+    frames.)"""
+    rng = np.random.default_rng(64)
+    N = 16
+    k = synthetic.spiral_trajectory(N, 2, 64, 1.0)
+    plan = recon.Plan(k, N, prec=prec)
+    plan.gram_kernel()
+    y = dev(rand_c(rng, 65, k.shape[0]))
+    x = dev(rand_c(rng, 65, N, N))
+    with pytest.raises(recon.ReconError):
+        plan.adjoint(y)
+    with pytest.raises(recon.ReconError):
+        plan.forward(x)
+    with pytest.raises(recon.ReconError):
+        plan.solve(y, 0.02, 0.1, 2)
+    with pytest.raises(recon.ReconError):
+        plan.begin(y=y, lam=0.02, delta=0.1)
+
+
+def test_no_batch_limit_with_fp64_adjoint():
+    """An FP64-adjoint plan takes 65 frames; frame 64 equals its lone result."""
+    rng = np.random.default_rng(65)
+    N = 16
+    k = synthetic.spiral_trajectory(N, 2, 64, 1.0)
+    plan = recon.Plan(k, N, prec=recon.FP64)
+    plan.gram_kernel()
+    y = dev(rand_c(rng, 65, k.shape[0]))
+    b = host(plan.adjoint(y))
+    b1 = host(plan.adjoint(y[64:65]))
+    np.testing.assert_array_equal(b[64], b1[0])
