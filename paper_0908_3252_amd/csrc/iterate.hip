@@ -272,12 +272,9 @@ __global__ __launch_bounds__(256) void k_update(
   constexpr int XT = (ROWS + 2) * W;      // rows n0-1 .. n0+ROWS
   constexpr int FFTB = ROWS * fft_team_lds<L, C>();
   constexpr int HX = RC::HX2;  // halo elements per thread (2 rows, j -> j/W, j%W)
-  // SEP: the x tile and the transform buffers are separate, and the x work
-  // runs before the inverse transform (the halo and old-x registers are free
-  // by then): the FP64 form at L <= 512, where registers bound occupancy.
-  // Otherwise they share LDS and the transform runs first.
-  constexpr bool SEP = sizeof(C) == 16 && L <= 512;
-  constexpr int SH = SEP ? XT + FFTB : (XT > FFTB ? XT : FFTB);
+  // The x tile and the transform buffers share LDS: the inverse transform
+  // runs first.
+  constexpr int SH = XT > FFTB ? XT : FFTB;
   // FP32 at L <= 512: the thread's twiddles in registers instead of an LDS
   // table (11% faster; the FP64 form has no registers to spare, and the
   // direction kernel gained nothing from it)
@@ -290,7 +287,7 @@ __global__ __launch_bounds__(256) void k_update(
   __shared__ double red[4 * 4];
   __shared__ R salpha;
   C* Xt = sh;                      // x, then x + alpha d (in place); row i <-> image row n0-1+i
-  C* fb = SEP ? sh + XT : sh;      // exchange buffers of the row transforms
+  C* fb = sh;                      // exchange buffers of the row transforms
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -303,10 +300,13 @@ __global__ __launch_bounds__(256) void k_update(
 #pragma unroll
     for (int e = 0; e < FftShape<L>::V; ++e) val[e] = row[t + e * TT];
   }
-  // LATE (FP64 at L = 1024, 16 transform values per thread): each image is
-  // loaded just before its first use, after the inverse transform, so that
-  // few of them are live at once (registers bound this form).
-  constexpr bool LATE = sizeof(C) == 16 && L >= 1024;
+  // LATE (the FP64 form): each image is loaded just before its first use,
+  // after the inverse transform, so that few of them are live at once.  At
+  // L <= 512 that leaves 125 registers and, with the transform buffers
+  // aliased to the x tile, <= 33 KB of LDS: 4 blocks per CU (an earlier form
+  // with all loads up front and separate buffers held 3; the update at 256^2
+  // went from 0.216 to 0.192 ms per 128 frames).
+  constexpr bool LATE = sizeof(C) == 16;
   C xo[EPT], dv[EPT], ro[EPT];
   C hx[HX], hd[HX];
   if constexpr (!LATE) {
@@ -335,12 +335,11 @@ __global__ __launch_bounds__(256) void k_update(
     if (threadIdx.x == 0) salpha = (R)alpha;
   }
 
-  if constexpr (!SEP) {
-    __syncthreads();  // twiddles, step length
-    if constexpr (TWR) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twr);
-    else fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
-    __syncthreads();  // the transform buffers become the x tile
-  }
+  // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
+  __syncthreads();  // twiddles, step length
+  if constexpr (TWR) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twr);
+  else fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
+  __syncthreads();  // the transform buffers become the x tile
   if constexpr (LATE) {
     load_own<L>(N, fo, n, t, x_old, xo);
     load_halo2<L>(N, fo, n0, x_old, hx);
@@ -403,8 +402,6 @@ __global__ __launch_bounds__(256) void k_update(
     }
   }
 
-  // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
-  if constexpr (SEP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
   __syncthreads();  // new x tile complete
   if constexpr (LATE) {
     load_own<L>(N, fo, n, t, r, ro);
