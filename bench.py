@@ -223,9 +223,9 @@ def main():
                          "(reference kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(frames and requests shard across GPUs with no exchange; "
-                                   "see the design notes)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(frames and requests are independent, so more GPUs "
+                                   "would each take a share of them with no exchange)"}))
         sys.exit(2)
 
     import torch
