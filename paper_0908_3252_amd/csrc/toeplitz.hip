@@ -105,7 +105,16 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
-  const int q0 = blockIdx.x * COLS;
+  // Row segments shorter than a cache line (FP32 at L = 1024: 8 columns, 64
+  // bytes): a frame's column blocks go to the 8 XCDs in contiguous ranges
+  // (workgroups are dispatched round-robin over the XCDs), so the two halves
+  // of a line are read by neighbouring blocks that share an L2.
+  int bx = blockIdx.x;
+  if constexpr (COLS * sizeof(C) < 128) {
+    const int nbx = gridDim.x;
+    if (nbx % 8 == 0) bx = (blockIdx.x % 8) * (nbx / 8) + blockIdx.x / 8;
+  }
+  const int q0 = bx * COLS;
   C* Tf = T + (size_t)f * N * L;
   double dqd = 0.0;
   // Stage the block's columns: every load of a thread is issued before the
@@ -184,7 +193,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   if (p3) {
     double v1[1] = {dqd};
     block_sum<1>(v1, red);
-    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + blockIdx.x] = v1[0];
+    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + bx] = v1[0];
   }
 }
 
