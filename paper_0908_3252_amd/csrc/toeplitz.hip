@@ -105,12 +105,14 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
-  // Row segments shorter than a cache line (FP32 at L = 1024: 8 columns, 64
-  // bytes): a frame's column blocks go to the 8 XCDs in contiguous ranges
-  // (workgroups are dispatched round-robin over the XCDs), so the two halves
-  // of a line are read by neighbouring blocks that share an L2.
+  // Row segments shorter than a cache line (FP32 at L >= 1024: 8 columns,
+  // 64 bytes), or a kernel spectrum larger than an XCD's L2 (L >= 1024): a
+  // frame's column blocks go to the 8 XCDs in contiguous ranges (workgroups
+  // are dispatched round-robin over the XCDs), so the two halves of a line
+  // are read by neighbouring blocks that share an L2, and each XCD reads
+  // only its eighth of the spectrum's columns.
   int bx = blockIdx.x;
-  if constexpr (COLS * sizeof(C) < 128) {
+  if constexpr (COLS * sizeof(C) < 128 || L >= 1024) {
     const int nbx = gridDim.x;
     if (nbx % 8 == 0) bx = (blockIdx.x % 8) * (nbx / 8) + blockIdx.x / 8;
   }
