@@ -3,8 +3,8 @@
 Section 3.3 minimises the convex criterion with a pseudo-conjugate-gradient
 method with a Polak-Ribiere correction, on the image-domain form of the data
 term (Section 3.4).  The paper does not spell out its line search (it spends
-three criterion evaluations per iteration, Section 5.2) and cites
-half-quadratic work for faster schemes (Section 6).  The reading used here:
+three criterion evaluations per iteration, Section 4.2) and cites
+half-quadratic work for faster schemes (Section 5).  The reading used here:
 
     x = x0 (zeros), r = Q x - b, g = 2 r + grad R(x), d = -g
     repeat iters times:
@@ -34,13 +34,45 @@ def _dot(a, b):
     return np.sum(np.conj(a) * b)
 
 
+def step_length(g, d, dQd, x, lam, delta, kind="hyperbolic", lam0=0.0,
+                alpha0=1.0, kind0="huber"):
+    """Minimiser along d of the half-quadratic majorant of J at x:
+    alpha = -Re<g, d> / (2 Re<d, Qd> + lam sum w(|Dx|) |Dd|^2
+                         [+ lam0 sum w0(|x|) |d|^2]),
+    with dQd = Re<d, Q d> and alpha = 0 when Re<g, d> = 0."""
+    gd = np.real(_dot(g, d))
+    curv = 2.0 * dQd + lam * penalty.smooth_curv(x, d, delta, kind)
+    if lam0:
+        curv = curv + lam0 * penalty.background_curv(x, d, alpha0, kind0)
+    return 0.0 if gd == 0.0 else -gd / curv
+
+
+def pr_plus_beta(g_new, g):
+    """Polak-Ribiere coefficient clipped at zero (PR+):
+    beta = max(0, Re<g_new, g_new - g> / <g, g>), 0 when <g, g> = 0."""
+    gg = np.real(_dot(g, g))
+    return 0.0 if gg == 0.0 else max(0.0, np.real(_dot(g_new, g_new - g)) / gg)
+
+
+def next_direction(g_new, d, beta):
+    """d_new = -g_new + beta d, or -g_new (restart) when that is not a
+    descent direction (Re<g_new, d_new> >= 0).  Returns (d_new, restarted)."""
+    dn = -g_new + beta * d
+    if np.real(_dot(g_new, dn)) >= 0.0:
+        return -g_new, True
+    return dn, False
+
+
 def solve(b, K, lam, delta, iters, kind="hyperbolic", x0=None, yy=None,
-          lam0=0.0, alpha0=1.0, kind0="huber", ls_steps=1, history=False):
+          lam0=0.0, alpha0=1.0, kind0="huber", ls_steps=1, history=False,
+          trace=None):
     """Run the fixed-budget minimisation for one frame.
 
     b: [N, N] complex (A^H y); K: [L, L] real Gram spectrum.
     Returns x, and with history=True also a dict with per-iteration J
     (needs yy = ||y||^2), ||g|| and the iteration state at the end.
+    trace: optional list; receives the initial (x, g, d) and, after every
+    iteration, (x, g, d, alpha, beta, restart) as dicts.
     """
     b = np.asarray(b, dtype=np.complex128)
     N = b.shape[-1]
@@ -54,6 +86,8 @@ def solve(b, K, lam, delta, iters, kind="hyperbolic", x0=None, yy=None,
     g = 2.0 * r + criterion.penalty_grad(x, lam, delta, kind, **pen)
     d = -g
     hist = dict(J=[], gnorm=[float(np.sqrt(np.real(_dot(g, g))))], restarts=0)
+    if trace is not None:
+        trace.append(dict(x=x, g=g, d=d))
 
     def J_now():
         return float(criterion.J_rewritten(x, yy, b, r + b, lam, delta, kind,
@@ -65,25 +99,20 @@ def solve(b, K, lam, delta, iters, kind="hyperbolic", x0=None, yy=None,
         Qd = Q(d)
         dQd = np.real(_dot(d, Qd))
         for _s in range(ls_steps):
-            gd = np.real(_dot(g, d))
-            curv = 2.0 * dQd + lam * penalty.smooth_curv(x, d, delta, kind)
-            if lam0:
-                curv = curv + lam0 * penalty.background_curv(x, d, alpha0, kind0)
-            alpha = 0.0 if gd == 0.0 else -gd / curv
+            alpha = step_length(g, d, dQd, x, lam, delta, kind, **pen)
             x = x + alpha * d
             r = r + alpha * Qd
             g_new = 2.0 * r + criterion.penalty_grad(x, lam, delta, kind, **pen)
             if _s + 1 < ls_steps:
                 g = g_new
-        gg_old = np.real(_dot(g, g))
-        beta = 0.0 if gg_old == 0.0 else max(
-            0.0, np.real(_dot(g_new, g_new - g)) / gg_old)
-        d = -g_new + beta * d
+        beta = pr_plus_beta(g_new, g)
+        d, restarted = next_direction(g_new, d, beta)
         g = g_new
-        if np.real(_dot(g, d)) >= 0.0:
-            d = -g
-            hist["restarts"] += 1
+        hist["restarts"] += int(restarted)
         hist["gnorm"].append(float(np.sqrt(np.real(_dot(g, g)))))
+        if trace is not None:
+            trace.append(dict(x=x, g=g, d=d, alpha=alpha, beta=beta,
+                              restart=restarted))
         if history and yy is not None:
             hist["J"].append(J_now())
     if history:
@@ -101,18 +130,12 @@ def step_from_state(x, r, g, d, K, lam, delta, kind="hyperbolic"):
     """
     N = x.shape[-1]
     Qd = toeplitz.apply_gram(d, K, N)
-    gd = np.real(_dot(g, d))
-    curv = 2.0 * np.real(_dot(d, Qd)) + lam * penalty.smooth_curv(x, d, delta, kind)
-    alpha = 0.0 if gd == 0.0 else -gd / curv
+    alpha = step_length(g, d, np.real(_dot(d, Qd)), x, lam, delta, kind)
     x1 = x + alpha * d
     r1 = r + alpha * Qd
     g1 = 2.0 * r1 + criterion.penalty_grad(x1, lam, delta, kind)
-    gg = np.real(_dot(g, g))
-    beta = 0.0 if gg == 0.0 else max(0.0, np.real(_dot(g1, g1 - g)) / gg)
-    d1 = -g1 + beta * d
-    restart = bool(np.real(_dot(g1, d1)) >= 0.0)
-    if restart:
-        d1 = -g1
+    beta = pr_plus_beta(g1, g)
+    d1, restart = next_direction(g1, d, beta)
     return (x1, r1, g1, d1), dict(alpha=alpha, beta=beta, restart=restart,
                                   Qd=Qd)
 

@@ -5,8 +5,8 @@ unit-variance noise draws.  It holds none of the reconstruction arithmetic
 (no Fourier operator, no Gram kernel, no penalty), so that the oracle and the
 HIP path can both consume the same inputs without sharing any method code.
 
-The paper's own data sets (the simulated two-vessel phantom of Section 5.1 and
-the GEMS phantom acquisition of Section 5.2) are not available; the recipes
+The paper's own data sets (the simulated two-vessel phantom of Section 4.1 and
+the GEMS phantom acquisition of Section 4.2) are not available; the recipes
 below stand in for them with the shapes the paper and the workload
 configurations use (interleaved spirals, k normalised to [-0.5, 0.5],
 complex images on an N x N grid, complex white Gaussian noise, Section 2).

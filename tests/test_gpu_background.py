@@ -2,7 +2,7 @@
 
     J(x) = ||y - A x||^2 + lambda sum phi_alpha1(|D x|) + lambda0 sum phi_alpha0(|x|)
 
-with the Huber function for both terms (the paper's choice, Section 5 uses
+with the Huber function for both terms (the paper's choice, Section 4.1 uses
 lambda1 = 0.1, alpha1 = 20, lambda0 = 0.5, alpha0 = 10 on its intensity
 scale; here the thresholds are scaled to the synthetic images' unit
 amplitudes).  The oracle's criterion, gradient and majorant curvature of the

@@ -84,7 +84,7 @@ def cart_grid(N):
 
 @pytest.mark.parametrize("N", [4, 8, 6])
 def test_P2_full_cartesian_is_dft(N):
-    """Section 4.1: on the complete Cartesian grid H is the (inverse) DFT
+    """Section 3.1: on the complete Cartesian grid H is the (inverse) DFT
     matrix, H^H H = I, so G is a delta and the Gram spectrum is 1."""
     rng = np.random.default_rng(3)
     k, P, Qg = cart_grid(N)
@@ -255,7 +255,7 @@ def test_P6_gradient_finite_differences(kind):
 
 def test_P7_quadratic_closed_form():
     """Quadratic penalty (Hunt): the minimiser is (A^H A + lam D^T D)^{-1} A^H y
-    (Section 4's least-squares closed form with the penalty added)."""
+    (Section 3's least-squares closed form with the penalty added)."""
     rng = np.random.default_rng(8)
     N, M = 6, 30
     k = rand_k(rng, M)
@@ -360,6 +360,184 @@ def test_P10_independent_quasi_newton():
     K = oracle.khat(k, N, 2 * N)
     xs = solver.solve(b, K, lam, delta, 600)
     np.testing.assert_allclose(xs, xq, atol=1e-7 * np.abs(xq).max())
+
+
+# ------------------------------------------------ iteration path (Section 3.3)
+
+def _dense_normal_matrix(k, N, lam):
+    """A^H A + lam D^T D from the explicit matrix of Section 2 and an explicit
+    difference matrix (row-major pixel index n*N + m)."""
+    A = nudft.dense_matrix(k, N)
+    n2 = N * N
+    rows = []
+    for n in range(N - 1):
+        for m in range(N):
+            e = np.zeros(n2)
+            e[(n + 1) * N + m], e[n * N + m] = 1.0, -1.0
+            rows.append(e)
+    for n in range(N):
+        for m in range(N - 1):
+            e = np.zeros(n2)
+            e[n * N + m + 1], e[n * N + m] = 1.0, -1.0
+            rows.append(e)
+    Dm = np.array(rows)
+    return A.conj().T @ A + lam * (Dm.T @ Dm)
+
+
+def _linear_cg_metrics(first=10):
+    """With the quadratic penalty the majorant step is the exact line
+    minimiser, so the pseudo-CG of Section 3.3 must be linear CG on
+    H = A^H A + lam D^T D over R^(2N^2) (inner product Re<a, b>): gradients
+    mutually orthogonal, directions H-conjugate (H as a dense matrix, not
+    the FFT form the oracle uses), and the gradient gone after 2 N^2 steps.
+    Returns (worst orthogonality, worst conjugacy over the first `first`
+    iterations, ||g_end|| / ||g_0||)."""
+    rng = np.random.default_rng(3)
+    N, M, lam = 4, 24, 0.02                 # condition number about 30
+    k = rand_k(rng, M)
+    y = rand_c(rng, M)
+    H = _dense_normal_matrix(k, N, lam)
+    trace = []
+    solver.solve(oracle.adjoint(y, k, N), oracle.khat(k, N, 2 * N), lam, 1.0,
+                 2 * N * N, kind="quadratic", trace=trace)
+    G = [t["g"].ravel() for t in trace]
+    D = [t["d"].ravel() for t in trace]
+
+    def cosine(a, b, op=None):
+        if op is None:
+            return abs(np.real(np.vdot(a, b))) / (np.linalg.norm(a) * np.linalg.norm(b))
+        return abs(np.real(np.vdot(a, op @ b))) / np.sqrt(
+            np.real(np.vdot(a, op @ a)) * np.real(np.vdot(b, op @ b)))
+
+    orth = max(cosine(G[i], G[j]) for i in range(first) for j in range(i))
+    conj = max(cosine(D[i], D[j], H) for i in range(first) for j in range(i))
+    return orth, conj, np.linalg.norm(G[-1]) / np.linalg.norm(G[0])
+
+
+def test_linear_cg_pin_quadratic_penalty():
+    """Section 3.3 with Hunt's quadratic penalty: PR+ with the exact step is
+    linear conjugate gradients (orthogonal gradients, conjugate directions,
+    termination within the 2 N^2 real dimensions)."""
+    orth, conj, ratio = _linear_cg_metrics()
+    assert orth < 1e-10 and conj < 1e-10, (orth, conj)
+    assert ratio <= 1e-10, ratio
+
+
+def _mm_pin(kind):
+    """The step length of one iteration against the minimiser of the
+    half-quadratic surrogate along d, built here from phi itself (its
+    derivative by a fourth-order central difference), the dense forward
+    matrix and a brute-force scalar minimisation:
+        S(a) = ||y - A(x + a d)||^2
+               + lam sum [phi(s) + (phi'(s) / (2 s)) (|D(x + a d)|^2 - s^2)],
+    s = |D x|.  Returns (relative step error, min over a grid of S - J)."""
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(21)
+    N, M, lam, delta = 5, 50, 0.4, 0.3
+    k = rand_k(rng, M)
+    y = rand_c(rng, M)
+    A = nudft.dense_matrix(k, N)
+    b = oracle.adjoint(y, k, N)
+    K = oracle.khat(k, N, 2 * N)
+    x = rand_c(rng, N, N)
+    r = oracle.apply_gram(x, K, N) - b
+    g = 2 * r + criterion.penalty_grad(x, lam, delta, kind)
+    d = -g + 0.3 * rand_c(rng, N, N)
+    _, sc = solver.step_from_state(x, r, g, d, K, lam, delta, kind)
+
+    def diffs(z):
+        return np.concatenate([(z[1:, :] - z[:-1, :]).ravel(),
+                               (z[:, 1:] - z[:, :-1]).ravel()])
+
+    def phi(t):
+        return penalty.phi(t, delta, kind)
+
+    s = np.abs(diffs(x))
+    h = 1e-5
+    dphi = (-phi(s + 2 * h) + 8 * phi(s + h) - 8 * phi(s - h) + phi(s - 2 * h)) / (12 * h)
+    w = dphi / s
+
+    def S(a):
+        z = x + a * d
+        t = np.abs(diffs(z))
+        return (np.sum(np.abs(y - A @ z.ravel()) ** 2)
+                + lam * np.sum(phi(s) + 0.5 * w * (t ** 2 - s ** 2)))
+
+    def J(a):
+        z = x + a * d
+        return np.sum(np.abs(y - A @ z.ravel()) ** 2) + lam * np.sum(phi(np.abs(diffs(z))))
+
+    a_star = minimize_scalar(S, bracket=(0.0, 1e-3), tol=1e-14).x
+    a = sc["alpha"]
+    gap = min(S(t) - J(t) for t in np.linspace(-2 * a, 4 * a, 61))
+    return abs(a - a_star) / abs(a_star), gap / abs(J(0.0))
+
+
+@pytest.mark.parametrize("kind", ["hyperbolic", "huber"])
+def test_mm_step_is_the_surrogate_minimiser(kind):
+    """The step of Section 3.3's iteration minimises the half-quadratic
+    majorant of J along d, and that majorant lies above J."""
+    err, gap = _mm_pin(kind)
+    assert err < 1e-8, err
+    assert gap > -1e-13, gap
+
+
+def _restart_state():
+    """A state (x, r, g, d) whose next direction -g1 + beta d is not a
+    descent direction: g is a small multiple of u, d = -u + c v with v the
+    part of the true gradient orthogonal to u, so beta is huge and
+    Re<g1, d> > 0."""
+    rng = np.random.default_rng(7)
+    N, M, lam, delta = 5, 40, 0.3, 0.2
+    k = rand_k(rng, M)
+    y = rand_c(rng, M)
+    b = oracle.adjoint(y, k, N)
+    K = oracle.khat(k, N, 2 * N)
+    x = rand_c(rng, N, N)
+    r = oracle.apply_gram(x, K, N) - b
+    g_true = 2 * r + criterion.penalty_grad(x, lam, delta)
+    u = rand_c(rng, N, N)
+    v = g_true - np.real(np.vdot(u, g_true)) / np.real(np.vdot(u, u)) * u
+    g = 1e-3 * u
+    d = -u + 5.0 * v / np.linalg.norm(v) * np.linalg.norm(u)
+    assert np.real(np.vdot(g, d)) < 0           # a descent direction for g
+    return (x, r, g, d), K, lam, delta
+
+
+def test_restart_gives_steepest_descent():
+    """Section 3.3's restart: when -g1 + beta d is not a descent direction
+    the next direction is exactly -g1; every direction is a descent one."""
+    state, K, lam, delta = _restart_state()
+    (x1, r1, g1, d1), sc = solver.step_from_state(*state, K, lam, delta)
+    assert sc["beta"] > 0 and sc["restart"]
+    assert np.array_equal(d1, -g1)
+    assert np.real(np.vdot(g1, d1)) < 0
+
+
+def test_planted_iteration_mistakes_are_caught(monkeypatch):
+    """beta = 0, a wrong-sign beta, the majorant curvature taken with the
+    weights of D d instead of D x, and a dropped restart each fail a pin."""
+    orig_beta = solver.pr_plus_beta
+    with monkeypatch.context() as mp:
+        mp.setattr(solver, "pr_plus_beta", lambda gn, g: 0.0)
+        orth, conj, ratio = _linear_cg_metrics()
+        assert ratio > 1e-6 and conj > 1e-3
+    with monkeypatch.context() as mp:
+        mp.setattr(solver, "pr_plus_beta", lambda gn, g: -orig_beta(gn, g))
+        orth, conj, ratio = _linear_cg_metrics()
+        assert ratio > 1e-6 and conj > 1e-3
+    orig_curv = penalty.smooth_curv
+    with monkeypatch.context() as mp:
+        mp.setattr(penalty, "smooth_curv",
+                   lambda x, d, delta, kind="hyperbolic": orig_curv(d, d, delta, kind))
+        for kind in ("hyperbolic", "huber"):
+            err, _ = _mm_pin(kind)
+            assert err > 1e-3, (kind, err)
+    with monkeypatch.context() as mp:
+        mp.setattr(solver, "next_direction", lambda gn, d, beta: (-gn + beta * d, False))
+        state, K, lam, delta = _restart_state()
+        (x1, r1, g1, d1), _ = solver.step_from_state(*state, K, lam, delta)
+        assert np.real(np.vdot(g1, d1)) >= 0
 
 
 # ---------------------------------------------------------------- planted mistakes
