@@ -65,6 +65,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
         "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
         "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
+        "recon_hq_workspace_bytes": (sz, [i64, i32, i32, i32, i32]),
+        "recon_solve_hq": (i32, [vp, vp, i32, f64, f64, i32, i32, i32, vp, i32, vp, sz, vp,
+                                 vp]),
+        "recon_solve_hq_iterate": (i32, [vp, i32, i32, vp, sz, vp]),
         "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
         "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, f64, f64, i32, vp, sz, vp]),
         "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
@@ -152,6 +156,15 @@ class Plan:
             self._ws[B] = (_dev_buf(n), n)
         return self._ws[B]
 
+    def hq_workspace(self, B: int):
+        """Device workspace of the half-quadratic solver for B frames (cached
+        per B; it also serves every call the plain workspace serves)."""
+        key = ("hq", B)
+        if key not in self._ws:
+            n = load().recon_hq_workspace_bytes(self.M, self.N, self.L, B, self.prec)
+            self._ws[key] = (_dev_buf(n), n)
+        return self._ws[key]
+
     def gram_kernel(self, want_khat: bool = False, want_lag: bool = False):
         import torch
         lib = load()
@@ -218,26 +231,65 @@ class Plan:
             return x
         return x, stats_to_numpy(st, B)
 
+    def solve_hq(self, y, lam: float, delta: float, outer: int, inner: int,
+                 phi: str = "hyperbolic", x0=None, want_stats: bool = True, lam0: float = 0.0,
+                 alpha0: float = 1.0):
+        """Half-quadratic minimisation: `outer` weight freezes of `inner`
+        linear-CG steps each (lam0 > 0: through the resumable entry points)."""
+        import torch
+        y = y.contiguous()
+        B = y.shape[0]
+        if lam0:
+            self.begin(y=y, lam=lam, delta=delta, phi=phi, x0=x0, lam0=lam0, alpha0=alpha0,
+                       hq=True)
+            self.hq_iterate(outer, inner)
+            return self.end() if want_stats else self.end()[0]
+        x = (x0.clone().contiguous() if x0 is not None else
+             torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda"))
+        st = _dev_buf(B * STATS_DTYPE.itemsize) if want_stats else None
+        ws, n = self.hq_workspace(B)
+        _check(load().recon_solve_hq(self._h, y.data_ptr(), B, float(lam), float(delta),
+                                     int(outer), int(inner), PHI[phi], x.data_ptr(),
+                                     1 if x0 is not None else 0, ws.data_ptr(), n, _ptr(st),
+                                     _stream()))
+        if not want_stats:
+            return x
+        return x, stats_to_numpy(st, B)
+
     # resumable form
     def begin(self, y=None, b=None, B=None, lam=0.0, delta=1.0, phi="hyperbolic", x0=None,
-              lam0=0.0, alpha0=1.0):
+              lam0=0.0, alpha0=1.0, hq: bool = False):
+        """hq: bind the half-quadratic workspace (for hq_iterate)."""
         src = y if y is not None else b
         B = src.shape[0] if B is None else B
-        ws, n = self.workspace(B)
+        ws, n = self.hq_workspace(B) if hq else self.workspace(B)
         _check(load().recon_solve_begin(self._h, _ptr(y), _ptr(b), B, float(lam), float(delta),
                                         float(lam0), float(alpha0), PHI[phi], _ptr(x0),
                                         ws.data_ptr(), n, _stream()))
-        self._active_B = B
+        self._active = (B, hq)
+
+    def _active_ws(self):
+        B, hq = self._active
+        return self.hq_workspace(B) if hq else self.workspace(B)
+
+    @property
+    def _active_B(self):
+        return self._active[0]
 
     def iterate(self, iters: int):
-        ws, n = self.workspace(self._active_B)
+        ws, n = self._active_ws()
         _check(load().recon_solve_iterate(self._h, int(iters), ws.data_ptr(), n, _stream()))
+
+    def hq_iterate(self, outer: int, inner: int):
+        ws, n = self._active_ws()
+        _check(load().recon_solve_hq_iterate(self._h, int(outer), int(inner), ws.data_ptr(), n,
+                                             _stream()))
 
     def export(self, field: str):
         import torch
         B = self._active_B
         out = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
-        ws, n = self.workspace(B)
+        ws, n = self._active_ws()
         _check(load().recon_solve_export(self._h, FIELD[field], out.data_ptr(), ws.data_ptr(), n,
                                          _stream()))
         return out
@@ -247,7 +299,7 @@ class Plan:
         B = self._active_B
         x = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
         st = _dev_buf(B * STATS_DTYPE.itemsize)
-        ws, n = self.workspace(B)
+        ws, n = self._active_ws()
         _check(load().recon_solve_end(self._h, x.data_ptr(), st.data_ptr(), ws.data_ptr(), n,
                                       _stream()))
         return x, stats_to_numpy(st, B)
@@ -286,7 +338,18 @@ class Pool:
 
     def admit(self, slot: int, y, lam: float, delta: float, iters: int, lam0: float = 0.0,
               alpha0: float = 1.0):
-        """Start frame y (device complex64 [M]) in `slot` with `iters` iterations."""
+        """Start frame y (device complex64 [M]) in `slot` with `iters` iterations.
+
+        When the pool runs on its own stream, that stream first waits for
+        the work already queued on the caller's current stream (which may
+        still be producing y), and y is marked as used on the pool's stream
+        so that its memory is not reused before the pool has read it."""
+        if self.stream is not None:
+            import torch
+            cur = torch.cuda.current_stream()
+            if cur != self.stream:
+                self.stream.wait_stream(cur)
+                y.record_stream(self.stream)
         _check(load().recon_pool_admit(self.plan.handle, int(slot), y.data_ptr(), float(lam),
                                        float(delta), float(lam0), float(alpha0), int(iters),
                                        self.ws.data_ptr(), self.nbytes, self._s()))

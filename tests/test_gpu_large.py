@@ -106,8 +106,11 @@ def test_large_gram_apply_sampled_and_energy(large):
 # from the FP64 oracle by 3.6e-8, 2.2e-7, 7.4e-6, 8.9e-5 and 3.4e-4 after
 # 1, 2, 5, 10 and 20 iterations, while rounding only b and the spectrum to
 # FP32 moves the 20-iteration result by 1.3e-6.  The bounds below are those
-# figures with a factor of about 5 for the different rounding pattern.
-LARGE_DRIFT = {1: 2e-7, 2: 1e-6, 5: 4e-5, 20: 2e-3}
+# figures with a factor of about 5 for the different rounding pattern, for
+# the runs where that stays under the required 1e-4; after 20 iterations
+# the FP32 iteration is held to 1e-4 and recorded as an expected failure
+# when it misses it.
+LARGE_DRIFT = {1: 2e-7, 2: 1e-6, 5: 4e-5}
 
 
 def test_large_end_to_end_short(large):
@@ -118,15 +121,54 @@ def test_large_end_to_end_short(large):
     b = oracle.adjoint(y[0], p.k, p.N)
     Kf = oracle.khat(p.k, p.N, p.L)
     yy = float(np.sum(np.abs(y[0].astype(np.complex128)) ** 2))
-    for iters, bound in LARGE_DRIFT.items():
+    for iters, bound in list(LARGE_DRIFT.items()) + [(20, 1e-4)]:
         x, st = plan.solve(dev(y), p.lam, p.delta, iters)
         xo, hist = oracle.solve(b, Kf, p.lam, p.delta, iters, yy=yy, history=True)
         e = rel(host(x)[0], xo)
         dj = abs(st["J"][0] - hist["J"][-1]) / abs(hist["J"][-1])
         print(f"large workload, {iters} iterations: rel {e:.3e} (bound {bound:.0e}); "
               f"J rel diff {dj:.2e}", flush=True)
-        assert e < bound
-        assert dj < 10 * bound
+        if iters in LARGE_DRIFT:
+            assert e < bound
+            assert dj < 10 * bound
+    if e >= 1e-4:
+        pytest.xfail(f"FP32 iteration: {e:.2e} after 20 iterations is over the 1e-4 bar "
+                     "(rounding amplified by the iteration; the FP64 iteration meets it)")
+
+
+@pytest.mark.timeout(900)
+def test_large_full_solve_fp64_iteration():
+    """Frame 0 of the large workload at its full budget (512^2, M = 262144,
+    L = 1024, 500 iterations) with the FP64 iteration, element by element
+    against the full FP64 oracle run, at the bar of the oracle's iterate
+    rounded to complex64 (1e-6).  The same frame with the FP32 iteration is
+    printed against 1e-4."""
+    p = synthetic.make_frames(5, frames=1)
+    y = p.measured(oracle.forward(p.x_true, p.k)).astype(np.complex64)
+    print(f"large workload frame 0: N={p.N} M={p.M} L={p.L} {p.iters} iterations", flush=True)
+    b = oracle.adjoint(y[0], p.k, p.N)
+    K = oracle.khat(p.k, p.N, p.L)
+    yy = float(np.sum(np.abs(y[0].astype(np.complex128)) ** 2))
+    xo, hist = oracle.solve(b, K, p.lam, p.delta, p.iters, yy=yy, history=True)
+    print("  oracle done", flush=True)
+    ref32 = xo.astype(np.complex64).astype(np.complex128)
+    out = {}
+    for prec in (recon.FP64_ITER64, recon.FP64):
+        plan = recon.Plan(p.k, p.N, p.L, prec=prec)
+        plan.gram_kernel()
+        x, st = plan.solve(dev(y), p.lam, p.delta, p.iters)
+        xg = host(x)[0]
+        out[prec] = (rel(xg, ref32), rel(xg, xo), st)
+        dj = abs(st["J"][0] - hist["J"][-1]) / abs(hist["J"][-1])
+        print(f"  prec={prec}: rel-L2 vs oracle {out[prec][1]:.3e} (vs rounded oracle "
+              f"{out[prec][0]:.3e}), J rel diff {dj:.2e}, status {st['status'][0]}", flush=True)
+        assert st["status"][0] == 0
+    e64 = out[recon.FP64_ITER64][0]
+    assert e64 < 1e-6, e64
+    j64 = out[recon.FP64_ITER64][2]["J"][0]
+    assert abs(j64 - hist["J"][-1]) < 1e-10 * abs(hist["J"][-1])
+    print(f"  FP32 iteration against the 1e-4 bar: {out[recon.FP64][1]:.3e} "
+          f"({'meets' if out[recon.FP64][1] < 1e-4 else 'misses'} it)")
 
 
 # Serving-size adjoints in every precision mode (batch 1, as admitted into a
@@ -169,19 +211,17 @@ def test_serving_size_adjoint_sampled(N, I, prec):
 # The precision form on the 256^2 series: four frames of the 128-frame
 # drifting series (first, two middle, last) solved together; each frame's
 # result is bitwise the one a larger batch gives (batch invariance), so these
-# are the per-frame errors of the series.  With the iteration in FP32 the
-# error is set by the trajectory, not by the adjoint: after 300 iterations
-# these frames are still ~30% from the minimiser and the iterate amplifies
-# per-step rounding ~1e4-fold (random relative perturbations of 6e-8 per step
-# already move it by 1e-4).  Measured with the FP32 iteration: 2e-4..1e-2
-# for every adjoint precision, changing from frame to frame and with any
-# change of rounding order; bounds 3e-2 (1e-1 with the BF16 x3 adjoint, whose
-# b errors are ~10x larger).  The FP64 iteration removes the amplified
-# rounding: its iterates equal the oracle's up to the final rounding to
-# complex64 (~2.5e-8), bound 1e-6.
+# are the per-frame errors of the series.  The FP64 iteration's iterates
+# equal the oracle's up to the final rounding to complex64 (~2.5e-8): bar
+# 1e-6.  With the iteration in FP32 the error is set by the trajectory, not
+# by the adjoint: after 300 iterations these frames are still ~30% from the
+# minimiser and the iterate amplifies per-step rounding ~1e4-fold (random
+# relative perturbations of 6e-8 per step already move it by 1e-4), so the
+# FP32-iteration rows (every adjoint precision) are held to the required
+# 1e-4 and recorded as expected failures when they miss it; the per-step
+# agreement of the FP32 iteration is checked by the shadow-step test below.
 SERIES_FRAMES = [0, 42, 85, 127]
-SERIES_BOUND = {recon.FP64: 3e-2, recon.FP32: 3e-2, recon.FP16X3: 3e-2, recon.BF16X3: 1e-1,
-                recon.FP64_ITER64: 1e-6}
+SERIES_BAR = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -217,7 +257,11 @@ def test_precision_form_series256(series256, prec):
     print("  per-frame rel-L2 vs FP64 oracle: " +
           ", ".join(f"f{f}={e:.2e}" for f, e in zip(SERIES_FRAMES, errs)))
     assert all(s == 0 for s in st["status"])
-    assert max(errs) < SERIES_BOUND[prec]
+    if prec == recon.FP64_ITER64:
+        assert max(errs) < 1e-6
+    elif max(errs) >= SERIES_BAR:
+        pytest.xfail(f"FP32 iteration (adjoint prec {prec}): worst frame {max(errs):.2e} "
+                     "misses the 1e-4 bar (rounding amplified by the unconverged iteration)")
 
 
 @pytest.mark.parametrize("frame", [85])
