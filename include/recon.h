@@ -228,6 +228,39 @@ recon_status_t recon_solve_end(recon_plan_t plan, float* x_out,
 recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
                                   void* ws, size_t ws_bytes, void* stream);
 
+/* ---- half-quadratic solver (Section 5's alternative to the pseudo-CG) --- */
+
+/* The paper's conclusion (Section 5) names a dual / half-quadratic
+ * optimisation [Idier01b] as a way to reduce the cost of the
+ * conjugate-gradient minimisation.  This is its multiplicative
+ * (Geman-Reynolds) form on the same criterion, operators and workspace:
+ * `outer` times, the penalty weights w = phi'(s)/s of the differences
+ * s = |D xbar| (and of the background term) are frozen at the current image
+ * xbar, and `inner` steps of linear conjugate gradients (exact steps,
+ * Polak-Ribiere coefficient with the descent safeguard, first direction -g)
+ * decrease the quadratic surrogate
+ *   ||y - A x||^2 + lam sum (w/2)|D x|^2 [+ lam0 sum (w0/2)|x|^2] + const,
+ * which lies above J and touches it at xbar, so J decreases at every outer
+ * iteration.  Each inner step applies Q once.
+ *   recon_hq_workspace_bytes: workspace of the half-quadratic solver (the
+ *                      recon_workspace_bytes layout plus two images); 0 on
+ *                      invalid sizes or precision.
+ *   recon_solve_hq:    as recon_solve (x0 = 0 or the contents of x), with
+ *                      outer x inner steps; stats.grad_ratio is the true
+ *                      gradient's norm ratio at the result.
+ *   recon_solve_hq_iterate: outer x inner more steps after recon_solve_begin
+ *                      (background term, b given, x0) on a workspace of
+ *                      recon_hq_workspace_bytes; recon_solve_end and
+ *                      recon_solve_export then apply as after
+ *                      recon_solve_iterate.  Slot pools are rejected. */
+size_t recon_hq_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B, int32_t prec);
+recon_status_t recon_solve_hq(recon_plan_t plan, const float* y, int32_t B, double lambda,
+                              double delta, int32_t outer, int32_t inner, int32_t phi, float* x,
+                              int32_t x_in_is_x0, void* ws, size_t ws_bytes,
+                              recon_stats_t* stats, void* stream);
+recon_status_t recon_solve_hq_iterate(recon_plan_t plan, int32_t outer, int32_t inner, void* ws,
+                                      size_t ws_bytes, void* stream);
+
 /* ---- slot pools: continuous batching of independent frames ------------- */
 
 /* A slot pool is a workspace sized for B frames (recon_workspace_bytes(B))

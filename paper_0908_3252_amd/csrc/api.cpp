@@ -110,13 +110,14 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec_full) {
 }
 
 struct WsLayout {
-  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, yyp, sc, adj, total;
+  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, yyp, sc, adj, xb, g, total;
   int rows, nb1, nb3, nb4, adj_splits;
 };
 
 // Images and the row-transform intermediate hold complex64 values, or
-// complex128 with the FP64 iteration (f64).
-WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64) {
+// complex128 with the FP64 iteration (f64).  hq: two more images after the
+// common layout (frozen image and gradient of the half-quadratic solver).
+WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64, bool hq = false) {
   WsLayout w{};
   const size_t es = f64 ? sizeof(double2) : sizeof(float2);
   const size_t img = (size_t)B * N * N * es;
@@ -158,6 +159,11 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64) {
     const size_t a32 = part_frames(w.adj_splits, adjoint_group(M, N));
     const size_t a64 = part_frames(adjoint64_splits(M, N), adjoint64_group(M, N));
     w.adj = take((a32 > a64 ? a32 : a64) * N * N * sizeof(double2));
+  }
+  w.xb = w.g = 0;
+  if (hq) {
+    w.xb = take(img);
+    w.g = take(img);
   }
   w.total = off;
   return w;
@@ -276,12 +282,14 @@ recon_status_t check_batch(recon_plan_t p, int32_t B) {
   return RECON_OK;
 }
 
-recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws* out) {
+recon_status_t check_ws(recon_plan_t p, void* ws, size_t ws_bytes, int32_t B, Ws* out,
+                        bool hq = false) {
   if (!ws) return fail(RECON_E_ARG, "workspace is NULL");
   if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
-  out->lay = ws_layout(p->M, p->N, p->L, B, p->f64);
+  out->lay = ws_layout(p->M, p->N, p->L, B, p->f64, hq);
   if (ws_bytes < out->lay.total)
-    return fail(RECON_E_NOMEM, "workspace smaller than recon_workspace_bytes");
+    return fail(RECON_E_NOMEM, hq ? "workspace smaller than recon_hq_workspace_bytes"
+                                  : "workspace smaller than recon_workspace_bytes");
   out->base = static_cast<char*>(ws);
   return RECON_OK;
 }
@@ -355,6 +363,13 @@ size_t recon_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B, int32_t
   if (check_geometry(M, N, L) != RECON_OK || B < 1) return 0;
   if (!valid_prec(prec, L)) return 0;
   return ws_layout(M, N, L, B, iter_f64(prec)).total;
+}
+
+size_t recon_hq_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t B, int32_t prec) {
+  if (L == 0) L = default_L(N);
+  if (check_geometry(M, N, L) != RECON_OK || B < 1) return 0;
+  if (!valid_prec(prec, L)) return 0;
+  return ws_layout(M, N, L, B, iter_f64(prec), true).total;
 }
 
 recon_status_t recon_plan(const double* traj, int64_t M, int32_t N, int32_t L, int32_t prec,
@@ -628,12 +643,64 @@ static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const 
   return RECON_OK;
 }
 
+// Half-quadratic minimisation: `outer` times, freeze the penalty weights at
+// the current image and run `inner` linear-CG steps on the surrogate; then
+// the true gradient's norm into the update partials (for the statistics).
+// The step counter k advances by one per inner step (x, d buffers as in
+// run_iterations).
+template <typename C, typename K>
+static recon_status_t run_hq_t(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0, int outer,
+                               int inner, const C* tw, const K* khat, hipStream_t s) {
+  const int N = p->N, L = p->L, B = c.B, R = w.lay.rows;
+  C* T = w.at<C>(w.lay.T);
+  C* r = w.at<C>(w.lay.r);
+  C* xb = w.at<C>(w.lay.xb);
+  C* g = w.at<C>(w.lay.g);
+  C* qd = w.at<C>(w.lay.qd);
+  int k = k0;
+  for (int o = 0; o < outer; ++o) {
+    HIP_TRY(launch_hq_freeze(N, B, w.lay.nb4, w.at<C>(w.lay.x[k & 1]), xb, w.dbl(w.lay.p4), s));
+    for (int it = 0; it < inner; ++it, ++k) {
+      C* d_old = w.at<C>(w.lay.d[k & 1]);
+      C* d_new = w.at<C>(w.lay.d[(k + 1) & 1]);
+      C* x_old = w.at<C>(w.lay.x[k & 1]);
+      C* x_new = w.at<C>(w.lay.x[(k + 1) & 1]);
+      {
+        TraceScope ts(TK_DIR, s);
+        HIP_TRY(launch_hq_dir(c.phi, N, R, B, r, d_old, d_new, g, x_old, xb, w.dbl(w.lay.p4),
+                              w.lay.nb4, w.dbl(w.lay.p1), w.params(), c.bg, s));
+      }
+      HIP_TRY(launch_rowfft_plain(L, N, B, d_new, T, tw, s));
+      {
+        TraceScope ts(TK_COL, s);
+        HIP_TRY(launch_colpass(L, N, B, T, khat, w.dbl(w.lay.p3), tw, w.params(), k, s));
+      }
+      HIP_TRY(launch_rowifft(L, N, B, T, qd, tw, w.params(), k, s));
+      {
+        TraceScope ts(TK_UPDATE, s);
+        HIP_TRY(launch_hq_update(c.phi, N, R, B, x_old, x_new, d_new, r, qd, g, xb,
+                                 w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3,
+                                 w.dbl(w.lay.p4), w.params(), c.bg, s));
+      }
+    }
+  }
+  HIP_TRY(launch_hq_gnorm(c.phi, N, R, B, w.at<C>(w.lay.x[k & 1]), r, w.dbl(w.lay.p4),
+                          w.params(), c.bg, s));
+  return RECON_OK;
+}
+
 extern "C" {
 
 static recon_status_t run_iterations(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
                                      int iters, hipStream_t s) {
   if (p->f64) return run_iterations_t(p, c, w, k0, iters, p->tw64(), p->khat64(), s);
   return run_iterations_t(p, c, w, k0, iters, p->tw(), p->khat(), s);
+}
+
+static recon_status_t run_hq(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0, int outer,
+                             int inner, hipStream_t s) {
+  if (p->f64) return run_hq_t(p, c, w, k0, outer, inner, p->tw64(), p->khat64(), s);
+  return run_hq_t(p, c, w, k0, outer, inner, p->tw(), p->khat(), s);
 }
 
 // Copy (FP32 iteration) or round (FP64 iteration) n complex values of the
@@ -664,6 +731,28 @@ recon_status_t recon_solve_iterate(recon_plan_t p, int32_t iters, void* ws, size
   if (st != RECON_OK) return st;
   std::lock_guard<std::mutex> lk(p->mu);
   p->solves[ws].iters = c.iters + iters;
+  return RECON_OK;
+}
+
+recon_status_t recon_solve_hq_iterate(recon_plan_t p, int32_t outer, int32_t inner, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(RECON_E_ARG, "NULL plan");
+  if (outer < 0 || inner < 0) return fail(RECON_E_ARG, "outer and inner must be >= 0");
+  if ((int64_t)outer * inner > INT32_MAX) return fail(RECON_E_RANGE, "too many iterations");
+  SolveCtx c;
+  recon_status_t st = get_ctx(p, ws, &c);
+  if (st != RECON_OK) return st;
+  if (c.pool) return fail(RECON_E_STATE, "workspace is a slot pool");
+  if ((int64_t)c.iters + (int64_t)outer * inner > INT32_MAX)
+    return fail(RECON_E_RANGE, "iteration counter overflow");
+  Ws w;
+  st = check_ws(p, ws, ws_bytes, c.B, &w, true);
+  if (st != RECON_OK) return st;
+  st = run_hq(p, c, w, c.iters, outer, inner, as_stream(stream));
+  if (st != RECON_OK) return st;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->solves[ws].iters = c.iters + outer * inner;
   return RECON_OK;
 }
 
@@ -756,6 +845,22 @@ recon_status_t recon_solve(recon_plan_t p, const float* y, int32_t B, double lam
                                         x_in_is_x0 ? x : nullptr, ws, ws_bytes, stream);
   if (st != RECON_OK) return st;
   st = recon_solve_iterate(p, iters, ws, ws_bytes, stream);
+  if (st != RECON_OK) return st;
+  return recon_solve_end(p, x, stats, ws, ws_bytes, stream);
+}
+
+recon_status_t recon_solve_hq(recon_plan_t p, const float* y, int32_t B, double lambda,
+                              double delta, int32_t outer, int32_t inner, int32_t phi, float* x,
+                              int32_t x_in_is_x0, void* ws, size_t ws_bytes, recon_stats_t* stats,
+                              void* stream) {
+  if (!p || !y || !x) return fail(RECON_E_ARG, "NULL argument");
+  if (outer < 0 || inner < 0) return fail(RECON_E_ARG, "outer and inner must be >= 0");
+  if (B >= 1 && ws_bytes < ws_layout(p->M, p->N, p->L, B, p->f64, true).total)
+    return fail(RECON_E_NOMEM, "workspace smaller than recon_hq_workspace_bytes");
+  recon_status_t st = recon_solve_begin(p, y, nullptr, B, lambda, delta, 0.0, 1.0, phi,
+                                        x_in_is_x0 ? x : nullptr, ws, ws_bytes, stream);
+  if (st != RECON_OK) return st;
+  st = recon_solve_hq_iterate(p, outer, inner, ws, ws_bytes, stream);
   if (st != RECON_OK) return st;
   return recon_solve_end(p, x, stats, ws, ws_bytes, stream);
 }

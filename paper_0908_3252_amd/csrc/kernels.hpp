@@ -120,6 +120,39 @@ hipError_t launch_export(int phi, int N, int R, int B, const double2* x, const d
                          const double2* d_old, const double* p4, int nb4, const FrameParam* fp,
                          float2* out, int dir, hipStream_t s);
 
+// ---- half-quadratic minimisation (Section 5's dual alternative) -------------
+// xb = x (weights frozen at the current image) and zeroed update partials.
+hipError_t launch_hq_freeze(int N, int B, int nb4, const float2* x, float2* xb, double* p4,
+                            hipStream_t s);
+hipError_t launch_hq_freeze(int N, int B, int nb4, const double2* x, double2* xb, double* p4,
+                            hipStream_t s);
+// Surrogate gradient g (stored), direction d_new (PR+ from p4), step partials
+// p1 [Re<g,d>, sum w(D xb)|D d|^2, sum w0(xb)|d|^2]; R rows per block.
+hipError_t launch_hq_dir(int phi, int N, int R, int B, const float2* r, const float2* d_old,
+                         float2* d_new, float2* g, const float2* x, const float2* xb,
+                         const double* p4, int nb4, double* p1, const FrameParam* fp, bool bg,
+                         hipStream_t s);
+hipError_t launch_hq_dir(int phi, int N, int R, int B, const double2* r, const double2* d_old,
+                         double2* d_new, double2* g, const double2* x, const double2* xb,
+                         const double* p4, int nb4, double* p1, const FrameParam* fp, bool bg,
+                         hipStream_t s);
+// Step alpha from p1 and the column pass's <d, Qd> partials p3; x_new = x_old
+// + alpha d, r += alpha qd; partials p4 for beta.
+hipError_t launch_hq_update(int phi, int N, int R, int B, const float2* x_old, float2* x_new,
+                            const float2* d, float2* r, const float2* qd, const float2* g_old,
+                            const float2* xb, const double* p1, int nb1, const double* p3,
+                            int nb3, double* p4, const FrameParam* fp, bool bg, hipStream_t s);
+hipError_t launch_hq_update(int phi, int N, int R, int B, const double2* x_old, double2* x_new,
+                            const double2* d, double2* r, const double2* qd,
+                            const double2* g_old, const double2* xb, const double* p1, int nb1,
+                            const double* p3, int nb3, double* p4, const FrameParam* fp, bool bg,
+                            hipStream_t s);
+// p4 = [|grad J(x)|^2, 0, 0, 0] per block (the true gradient, weights from x).
+hipError_t launch_hq_gnorm(int phi, int N, int R, int B, const float2* x, const float2* r,
+                           double* p4, const FrameParam* fp, bool bg, hipStream_t s);
+hipError_t launch_hq_gnorm(int phi, int N, int R, int B, const double2* x, const double2* r,
+                           double* p4, const FrameParam* fp, bool bg, hipStream_t s);
+
 // ---- NUDFT (Section 2, Appendix A.2) -------------------------------------------
 // Phasor tables E[l][j] = exp(i 2 pi k_l j), j < N, FP32 complex, for both
 // axes: ex from k_x, ey from k_y.  k: device float64 [M][2].
