@@ -235,3 +235,27 @@ def serving_requests(count: int, rate: float, seed: int = 4):
                         delta=delta, iters=300, L=2 * N, noise_c=0.01,
                         x_true=x, noise=nz))
     return out
+
+
+def roi_masks(x_true: np.ndarray, radius: int = 2):
+    """Regions of interest of a phantom for the gridding comparison (the
+    paper's ROI1, a central square, and ROI2, a region of constant value).
+
+    ROI1: the central square of side N/4.  ROI2: the pixels whose whole
+    (2 radius + 1)^2 neighbourhood holds one non-zero value, restricted to
+    the value that covers the most such pixels (a flat interior region of
+    the piecewise-constant phantom).  Returns two boolean [N, N] masks."""
+    N = x_true.shape[-1]
+    roi1 = np.zeros((N, N), dtype=bool)
+    a = N // 2 - N // 8
+    roi1[a:a + N // 4, a:a + N // 4] = True
+    flat = x_true != 0
+    for dn in range(-radius, radius + 1):
+        for dm in range(-radius, radius + 1):
+            sh = np.roll(np.roll(x_true, dn, axis=0), dm, axis=1)
+            flat &= sh == x_true
+    flat[:radius, :] = flat[-radius:, :] = False
+    flat[:, :radius] = flat[:, -radius:] = False
+    vals, counts = np.unique(x_true[flat], return_counts=True)
+    roi2 = flat & (x_true == vals[np.argmax(counts)]) if len(vals) else flat
+    return roi1, roi2
