@@ -261,6 +261,65 @@ recon_status_t recon_solve_hq(recon_plan_t plan, const float* y, int32_t B, doub
 recon_status_t recon_solve_hq_iterate(recon_plan_t plan, int32_t outer, int32_t inner, void* ws,
                                       size_t ws_bytes, void* stream);
 
+/* ---- convolution gridding and non-uniform FFT -------------------------- */
+
+/* Section 1 describes the gridding reconstruction the method is compared
+ * with: weighting of the samples for their non-uniform density, resampling
+ * onto a Cartesian grid with a convolution kernel, an FFT, and correction of
+ * the kernel's apodization; Section 4.1 uses a 7 x 7 Kaiser-Bessel kernel.
+ * Section 5 proposes the same non-uniform FFT machinery to speed up the
+ * precomputation of D = A^H y and of the Gram kernel.  All of it runs in
+ * FP64 on the device:
+ *   type-1 sum  out[n][m] = sum_l c_l exp(-i 2 pi (ky_l (n - h) + kx_l (m - h)))
+ *   c spread onto a G x G grid with phi(g1 - G ky) phi(g2 - G kx), the
+ *   Kaiser-Bessel kernel phi(t) = I0(beta sqrt(1 - (2t/W)^2)), |t| <= W/2;
+ *   forward 2D FFT; outputs divided by the kernel's Fourier transform.
+ * With grid oversampling G/N >= 2 and the default beta
+ * (pi sqrt(W^2 / s^2 (s - 1/2)^2 - 0.8), s = G/N) the relative error of the
+ * sums is bounded by about 4 / I0(beta): 4e-4 (W = 5), 3.5e-6 (W = 7),
+ * 3.4e-8 (W = 9), 3.3e-10 (W = 11), 3.1e-12 (W = 13), from the kernel's jump
+ * at the edge of its support.
+ *
+ * A grid plan holds, in caller memory (recon_grid_bytes), the trajectory,
+ * the per-sample kernel weights and footprints, per-tile sample lists (built
+ * on the host: the plan call synchronises `stream`), the apodization
+ * correction and the FFT twiddles.  traj: host float64 [M][2] (kx, ky) as
+ * for recon_plan; N: output size (N x N), 2 N <= G; G: power of two in
+ * [64, 2048] (0: the smallest >= 2N); W: kernel width in [2, 16]; beta: the
+ * kernel's shape (0: the default above).  M <= 2^29 - 1.
+ *   recon_grid_adjoint: out[f] = (1/N) sum_l w_l y[f]_l exp(-i 2 pi (kx_l m + ky_l n)),
+ *       n, m < N (Eq. AnnMatGD with weights; w == NULL means 1): with
+ *       density weights it is the gridding reconstruction, without them the
+ *       NUFFT form of D.  y: device complex64 [B][M]; w: device float64 [M];
+ *       out: device complex64 [B][N][N]; ws >= recon_grid_workspace_bytes(B).
+ *   recon_grid_density: density-compensation weights by the fixed-point
+ *       iteration of Pipe and Menon (the paper's [Pipe99]): from w = 1,
+ *       `iters` times w <- w / (I S w) with S the spreading of real weights
+ *       and I its adjoint (interpolation); finally scaled by
+ *       phi_hat(0)^4 / (G/N)^2 so that a uniform Cartesian grid of spacing
+ *       1/N gets weights ~1.  w: device float64 [M] (output).
+ *   recon_gram_kernel_nufft: the plan's Gram kernel (as recon_gram_kernel)
+ *       with the lag kernel h[a][b] = (1/N^2) sum_l exp(-i 2 pi (ky a + kx b))
+ *       computed by a type-1 sum on 2N outputs (grid of 4N rounded up to a
+ *       power of two, N <= 512) instead of the exact sums; within the bound
+ *       above for width W.  ws >= recon_gram_nufft_workspace_bytes (which
+ *       also holds that sum's own grid plan; the call synchronises `stream`). */
+typedef struct recon_grid_s* recon_grid_t;
+size_t recon_grid_bytes(int64_t M, int32_t N, int32_t G, int32_t W);
+recon_status_t recon_grid_plan(const double* traj, int64_t M, int32_t N, int32_t G, int32_t W,
+                               double beta, void* mem, size_t mem_bytes, void* stream,
+                               recon_grid_t* out);
+recon_status_t recon_grid_info(recon_grid_t grid, int32_t* G, int32_t* W, double* beta);
+void recon_grid_destroy(recon_grid_t grid);
+size_t recon_grid_workspace_bytes(recon_grid_t grid, int32_t B);
+recon_status_t recon_grid_adjoint(recon_grid_t grid, const float* y, const double* w, int32_t B,
+                                  float* out, void* ws, size_t ws_bytes, void* stream);
+recon_status_t recon_grid_density(recon_grid_t grid, int32_t iters, double* w, void* ws,
+                                  size_t ws_bytes, void* stream);
+size_t recon_gram_nufft_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t W);
+recon_status_t recon_gram_kernel_nufft(recon_plan_t plan, int32_t W, void* ws, size_t ws_bytes,
+                                       float* khat_out, double* lag_out, void* stream);
+
 /* ---- slot pools: continuous batching of independent frames ------------- */
 
 /* A slot pool is a workspace sized for B frames (recon_workspace_bytes(B))

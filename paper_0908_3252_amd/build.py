@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RECON_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "nudft.hip", "nudft64.hip", "nudft_split.hip", "gram.hip", "toeplitz.hip",
-           "cg.hip", "iterate.hip", "hq.hip"]
+           "cg.hip", "iterate.hip", "hq.hip", "grid.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -229,6 +229,236 @@ struct SolveCtx {
   std::vector<int32_t> stop_at;   // per slot (pool only): k at which the slot stops
 };
 
+// ---- convolution gridding / NUFFT geometry ---------------------------------
+constexpr int GRID_TILE = 32;    // grid tile side of the spreading kernel
+constexpr int GRID_GROUP = 16;   // frames gridded per round (bounds the workspace)
+
+struct GridGeom {
+  int64_t M;
+  int Nout, G, W, h, phase;
+  double beta;
+};
+
+struct GridLayout {
+  size_t k, base, wy, wx, pf, toff, tent, deap, tw, total;
+  int ntiles;
+};
+
+// Kaiser-Bessel shape for width W at oversampling sigma (minimal-oversampling rule).
+double kb_beta(int W, double sigma) {
+  const double a = (double)W / sigma * (sigma - 0.5);
+  return M_PI * std::sqrt(a * a - 0.8);
+}
+
+// Fourier transform of the Kaiser-Bessel kernel (closed form).
+double kb_hat(double nu, int W, double beta) {
+  const double z2 = beta * beta - (M_PI * W * nu) * (M_PI * W * nu);
+  if (z2 > 1e-12) {
+    const double z = std::sqrt(z2);
+    return W * std::sinh(z) / z;
+  }
+  if (z2 < -1e-12) {
+    const double z = std::sqrt(-z2);
+    return W * std::sin(z) / z;
+  }
+  return (double)W;
+}
+
+GridLayout grid_layout(const GridGeom& g) {
+  GridLayout l{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  l.ntiles = (g.G / GRID_TILE) * (g.G / GRID_TILE);
+  l.k = take((size_t)g.M * 2 * sizeof(double));
+  l.base = take((size_t)g.M * sizeof(int2));
+  l.wy = take((size_t)g.M * g.W * sizeof(double));
+  l.wx = take((size_t)g.M * g.W * sizeof(double));
+  l.pf = take((size_t)g.M * sizeof(double2));
+  l.toff = take((size_t)(l.ntiles + 1) * sizeof(int));
+  l.tent = take((size_t)g.M * 4 * sizeof(int));  // a footprint touches at most 2 x 2 tiles
+  l.deap = take((size_t)g.Nout * sizeof(double));
+  l.tw = take((size_t)g.G * sizeof(double2));
+  l.total = off;
+  return l;
+}
+
+recon_status_t check_grid_geom(const GridGeom& g) {
+  if (g.M < 1 || g.M > (int64_t)0x1fffffff) return fail(RECON_E_RANGE, "M must be in [1, 2^29-1]");
+  if (!is_pow2(g.G) || g.G < 64 || g.G > 2048)
+    return fail(RECON_E_RANGE, "grid size must be a power of two in [64, 2048]");
+  if (g.Nout < 2 || 2 * g.Nout > g.G) return fail(RECON_E_RANGE, "need 2 <= N and 2 N <= grid size");
+  if (g.W < 2 || g.W > 16) return fail(RECON_E_RANGE, "kernel width must be in [2, 16]");
+  if (!(g.beta > 0.0) || !std::isfinite(g.beta)) return fail(RECON_E_RANGE, "bad kernel shape");
+  return RECON_OK;
+}
+
+// Per-tile sample lists (host counting sort), apodization correction and
+// FFT twiddles uploaded to mem; per-sample weights computed on the device.
+// Synchronises `s` (host staging buffers).
+recon_status_t build_grid(const GridGeom& g, const double* traj, char* mem, const GridLayout& l,
+                          hipStream_t s) {
+  const int nt = g.G / GRID_TILE;
+  std::vector<int> cnt((size_t)l.ntiles + 1, 0);
+  std::vector<int> tiles((size_t)g.M * 4);
+  std::vector<unsigned char> ntl((size_t)g.M);
+  for (int64_t i = 0; i < g.M; ++i) {
+    int ty[2], tx[2], ny = 0, nx = 0;
+    const double u[2] = {(double)g.G * traj[2 * i + 1], (double)g.G * traj[2 * i]};
+    for (int ax = 0; ax < 2; ++ax) {
+      const int64_t g0 = (int64_t)std::floor(u[ax] - 0.5 * g.W) + 1;
+      int* t = ax == 0 ? ty : tx;
+      int& n = ax == 0 ? ny : nx;
+      for (int j = 0; j < g.W; ++j) {
+        const int gi = (int)(((g0 + j) % g.G + g.G) % g.G);
+        const int ti = gi / GRID_TILE;
+        bool seen = false;
+        for (int q = 0; q < n; ++q) seen |= t[q] == ti;
+        if (!seen) t[n++] = ti;
+      }
+    }
+    int c = 0;
+    for (int a = 0; a < ny; ++a)
+      for (int b = 0; b < nx; ++b) {
+        const int tile = ty[a] * nt + tx[b];
+        tiles[(size_t)i * 4 + c++] = tile;
+        ++cnt[tile + 1];
+      }
+    ntl[i] = (unsigned char)c;
+  }
+  for (int t = 0; t < l.ntiles; ++t) cnt[t + 1] += cnt[t];
+  std::vector<int> toff(cnt);
+  std::vector<int> tent((size_t)cnt[l.ntiles]);
+  for (int64_t i = 0; i < g.M; ++i)
+    for (int c = 0; c < ntl[i]; ++c) tent[cnt[tiles[(size_t)i * 4 + c]]++] = (int)i;
+  std::vector<double> deap(g.Nout);
+  for (int n = 0; n < g.Nout; ++n) deap[n] = 1.0 / kb_hat((double)(n - g.h) / g.G, g.W, g.beta);
+  std::vector<double2> tw(g.G);
+  for (int i = 0; i < g.G; ++i) {
+    const double a = -2.0 * M_PI * (double)i / (double)g.G;
+    tw[i] = make_double2(std::cos(a), std::sin(a));
+  }
+  hipError_t e = hipMemcpyAsync(mem + l.k, traj, (size_t)g.M * 2 * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(mem + l.toff, toff.data(), toff.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !tent.empty())
+    e = hipMemcpyAsync(mem + l.tent, tent.data(), tent.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(mem + l.deap, deap.data(), deap.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(mem + l.tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_grid_weights(g.M, g.G, g.W, g.beta, g.h, g.phase,
+                            reinterpret_cast<const double*>(mem + l.k),
+                            reinterpret_cast<int2*>(mem + l.base), reinterpret_cast<double*>(mem + l.wy),
+                            reinterpret_cast<double*>(mem + l.wx),
+                            reinterpret_cast<double2*>(mem + l.pf), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "grid plan");
+  return RECON_OK;
+}
+
+// Type-1 sums of B frames (or of the real weights when y == NULL, B = 1) in
+// rounds of GRID_GROUP frames.  gridbuf: [GRID_GROUP][G][G], rows:
+// [GRID_GROUP][G][Nout] (FP64 complex).
+template <typename O>
+recon_status_t grid_type1(const GridGeom& g, const char* mem, const GridLayout& l, const float2* y,
+                          const double* w, double scale, int B, O* out, double2* gridbuf,
+                          double2* rows, hipStream_t s) {
+  for (int f0 = 0; f0 < B; f0 += GRID_GROUP) {
+    const int nb = B - f0 < GRID_GROUP ? B - f0 : GRID_GROUP;
+    HIP_TRY(launch_grid_spread(g.G, g.W, nb, g.M, reinterpret_cast<const int*>(mem + l.toff),
+                               reinterpret_cast<const int*>(mem + l.tent),
+                               reinterpret_cast<const int2*>(mem + l.base),
+                               reinterpret_cast<const double*>(mem + l.wy),
+                               reinterpret_cast<const double*>(mem + l.wx),
+                               reinterpret_cast<const double2*>(mem + l.pf),
+                               y ? y + (size_t)f0 * g.M : nullptr, w, scale, gridbuf, s));
+    HIP_TRY(launch_grid_fft(g.G, g.Nout, g.h, nb, gridbuf, rows,
+                            reinterpret_cast<const double*>(mem + l.deap),
+                            out + (size_t)f0 * g.Nout * g.Nout,
+                            reinterpret_cast<const double2*>(mem + l.tw), s));
+  }
+  return RECON_OK;
+}
+
+int grid_default_G(int Nout) {
+  int G = 64;
+  while (G < 2 * Nout) G *= 2;
+  return G;
+}
+
+}  // namespace
+
+struct recon_grid_s {
+  GridGeom geom;
+  GridLayout lay;
+  char* mem;
+};
+
+namespace {
+
+struct GridWs {
+  size_t grid, rows, total;
+};
+
+GridWs grid_ws_layout(const GridGeom& g, int B) {
+  GridWs w{};
+  const int nb = B < GRID_GROUP ? B : GRID_GROUP;
+  size_t off = 0;
+  w.grid = off;
+  off = align_up(off + (size_t)nb * g.G * g.G * sizeof(double2));
+  w.rows = off;
+  off = align_up(off + (size_t)nb * g.G * g.Nout * sizeof(double2));
+  w.total = off;
+  return w;
+}
+
+// Geometry of the lag-kernel type-1 sum of a plan: 2N outputs (lags
+// -N .. N-1), grid >= 4N, no sample phase.
+GridGeom lag_geom(int64_t M, int N, int W) {
+  GridGeom g{};
+  g.M = M;
+  g.Nout = 2 * N;
+  g.G = grid_default_G(2 * N);
+  g.W = W;
+  g.h = N;
+  g.phase = 0;
+  g.beta = kb_beta(W, (double)g.G / g.Nout);
+  return g;
+}
+
+struct GramNufftWs {
+  GridGeom geom;
+  GridLayout lay;
+  size_t gplan, ones, grid, rows, lag2n, emb, emb2, total;
+};
+
+GramNufftWs gram_nufft_layout(int64_t M, int N, int L, int W) {
+  GramNufftWs w{};
+  w.geom = lag_geom(M, N, W);
+  w.lay = grid_layout(w.geom);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  w.gplan = take(w.lay.total);
+  w.ones = take((size_t)M * sizeof(double));
+  w.grid = take((size_t)w.geom.G * w.geom.G * sizeof(double2));
+  w.rows = take((size_t)w.geom.G * w.geom.Nout * sizeof(double2));
+  w.lag2n = take((size_t)w.geom.Nout * w.geom.Nout * sizeof(double2));
+  w.emb = take((size_t)L * L * sizeof(double2));
+  w.emb2 = take((size_t)L * L * sizeof(double2));
+  w.total = off;
+  return w;
+}
+
 }  // namespace
 
 struct recon_plan_s {
@@ -1063,6 +1293,158 @@ int32_t recon_trace_read(float* ms_out, int32_t n) {
   }
   if (first < 0) return (ms_out && n >= 0) ? 0 : -1;
   return recon_trace_read_kind(first, ms_out, n);
+}
+
+// ---- convolution gridding / NUFFT ------------------------------------------
+
+static GridGeom adjoint_geom(int64_t M, int32_t N, int32_t G, int32_t W, double beta) {
+  GridGeom g{};
+  g.M = M;
+  g.Nout = N;
+  g.G = G ? G : grid_default_G(N);
+  g.W = W;
+  g.h = N / 2;
+  g.phase = 1;
+  g.beta = beta > 0.0 ? beta : kb_beta(W, (double)g.G / N);
+  return g;
+}
+
+size_t recon_grid_bytes(int64_t M, int32_t N, int32_t G, int32_t W) {
+  const GridGeom g = adjoint_geom(M, N, G, W, 0.0);
+  if (N < 2 || W < 2 || W > 16 || check_grid_geom(g) != RECON_OK) return 0;
+  return grid_layout(g).total;
+}
+
+recon_status_t recon_grid_plan(const double* traj, int64_t M, int32_t N, int32_t G, int32_t W,
+                               double beta, void* mem, size_t mem_bytes, void* stream,
+                               recon_grid_t* out) {
+  g_last_error.clear();
+  if (!traj || !mem || !out) return fail(RECON_E_ARG, "NULL argument");
+  if (N < 2) return fail(RECON_E_RANGE, "N must be >= 2");
+  if (W < 2 || W > 16) return fail(RECON_E_RANGE, "kernel width must be in [2, 16]");
+  if (beta < 0.0 || !std::isfinite(beta)) return fail(RECON_E_RANGE, "beta must be >= 0");
+  const GridGeom g = adjoint_geom(M, N, G, W, beta);
+  recon_status_t st = check_grid_geom(g);
+  if (st != RECON_OK) return st;
+  for (int64_t i = 0; i < 2 * M; ++i) {
+    const double v = traj[i];
+    if (!std::isfinite(v) || std::fabs(v) > 0.5)
+      return fail(RECON_E_RANGE, "trajectory entries must be finite with |k| <= 0.5");
+  }
+  const GridLayout l = grid_layout(g);
+  if (mem_bytes < l.total) return fail(RECON_E_NOMEM, "grid memory smaller than recon_grid_bytes");
+  st = build_grid(g, traj, static_cast<char*>(mem), l, as_stream(stream));
+  if (st != RECON_OK) return st;
+  auto* p = new recon_grid_s();
+  p->geom = g;
+  p->lay = l;
+  p->mem = static_cast<char*>(mem);
+  *out = p;
+  return RECON_OK;
+}
+
+void recon_grid_destroy(recon_grid_t g) { delete g; }
+
+recon_status_t recon_grid_info(recon_grid_t g, int32_t* G, int32_t* W, double* beta) {
+  if (!g) return fail(RECON_E_ARG, "NULL grid plan");
+  if (G) *G = g->geom.G;
+  if (W) *W = g->geom.W;
+  if (beta) *beta = g->geom.beta;
+  return RECON_OK;
+}
+
+size_t recon_grid_workspace_bytes(recon_grid_t g, int32_t B) {
+  if (!g || B < 1) return 0;
+  return grid_ws_layout(g->geom, B).total;
+}
+
+recon_status_t recon_grid_adjoint(recon_grid_t g, const float* y, const double* w, int32_t B,
+                                  float* out, void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!g || !y || !out || !ws) return fail(RECON_E_ARG, "NULL argument");
+  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  const GridWs wl = grid_ws_layout(g->geom, B);
+  if (ws_bytes < wl.total) return fail(RECON_E_NOMEM, "workspace smaller than recon_grid_workspace_bytes");
+  char* base = static_cast<char*>(ws);
+  return grid_type1(g->geom, g->mem, g->lay, reinterpret_cast<const float2*>(y), w,
+                    1.0 / g->geom.Nout, B, reinterpret_cast<float2*>(out),
+                    reinterpret_cast<double2*>(base + wl.grid),
+                    reinterpret_cast<double2*>(base + wl.rows), as_stream(stream));
+}
+
+recon_status_t recon_grid_density(recon_grid_t g, int32_t iters, double* w, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!g || !w || !ws) return fail(RECON_E_ARG, "NULL argument");
+  if (iters < 1) return fail(RECON_E_ARG, "iters must be >= 1");
+  const GridWs wl = grid_ws_layout(g->geom, 1);
+  if (ws_bytes < wl.total) return fail(RECON_E_NOMEM, "workspace smaller than recon_grid_workspace_bytes");
+  hipStream_t s = as_stream(stream);
+  const GridGeom& gg = g->geom;
+  const GridLayout& l = g->lay;
+  double2* grid = reinterpret_cast<double2*>(static_cast<char*>(ws) + wl.grid);
+  const double sigma = (double)gg.G / gg.Nout;
+  const double h0 = kb_hat(0.0, gg.W, gg.beta);
+  const double final_scale = h0 * h0 * h0 * h0 / (sigma * sigma);
+  HIP_TRY(launch_fill_f64((size_t)gg.M, 1.0, w, s));
+  for (int it = 0; it < iters; ++it) {
+    HIP_TRY(launch_grid_spread(gg.G, gg.W, 1, gg.M, reinterpret_cast<const int*>(g->mem + l.toff),
+                               reinterpret_cast<const int*>(g->mem + l.tent),
+                               reinterpret_cast<const int2*>(g->mem + l.base),
+                               reinterpret_cast<const double*>(g->mem + l.wy),
+                               reinterpret_cast<const double*>(g->mem + l.wx),
+                               reinterpret_cast<const double2*>(g->mem + l.pf), nullptr, w, 1.0,
+                               grid, s));
+    HIP_TRY(launch_dcf_update(gg.G, gg.W, gg.M, reinterpret_cast<const int2*>(g->mem + l.base),
+                              reinterpret_cast<const double*>(g->mem + l.wy),
+                              reinterpret_cast<const double*>(g->mem + l.wx), grid, w,
+                              it + 1 == iters ? final_scale : 1.0, s));
+  }
+  return RECON_OK;
+}
+
+size_t recon_gram_nufft_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t W) {
+  if (L == 0) L = default_L(N);
+  if (check_geometry(M, N, L) != RECON_OK || W < 2 || W > 16) return 0;
+  const GramNufftWs w = gram_nufft_layout(M, N, L, W);
+  if (check_grid_geom(w.geom) != RECON_OK) return 0;
+  return w.total;
+}
+
+recon_status_t recon_gram_kernel_nufft(recon_plan_t p, int32_t W, void* ws, size_t ws_bytes,
+                                       float* khat_out, double* lag_out, void* stream) {
+  g_last_error.clear();
+  if (!p || !ws) return fail(RECON_E_ARG, "NULL argument");
+  if (W < 2 || W > 16) return fail(RECON_E_RANGE, "kernel width must be in [2, 16]");
+  const GramNufftWs w = gram_nufft_layout(p->M, p->N, p->L, W);
+  recon_status_t st = check_grid_geom(w.geom);
+  if (st != RECON_OK) return st;
+  if (ws_bytes < w.total) return fail(RECON_E_NOMEM, "workspace smaller than recon_gram_nufft_workspace_bytes");
+  hipStream_t s = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  // the trajectory is on the device in the plan; the host binning needs it
+  std::vector<double> traj((size_t)p->M * 2);
+  HIP_TRY(hipMemcpyAsync(traj.data(), p->k(), traj.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  char* gmem = base + w.gplan;
+  st = build_grid(w.geom, traj.data(), gmem, w.lay, s);
+  if (st != RECON_OK) return st;
+  double* ones = reinterpret_cast<double*>(base + w.ones);
+  HIP_TRY(launch_fill_f64((size_t)p->M, 1.0, ones, s));
+  double2* lag2n = reinterpret_cast<double2*>(base + w.lag2n);
+  {
+    TraceScope ts(TK_GRAM, s);
+    st = grid_type1(w.geom, gmem, w.lay, nullptr, ones, 1.0 / ((double)p->N * p->N), 1, lag2n,
+                    reinterpret_cast<double2*>(base + w.grid),
+                    reinterpret_cast<double2*>(base + w.rows), s);
+    if (st != RECON_OK) return st;
+  }
+  double2* emb = reinterpret_cast<double2*>(base + w.emb);
+  HIP_TRY(launch_lag_embed(p->N, p->L, lag2n, lag_out, emb, s));
+  HIP_TRY(launch_spectrum_f64(p->L, emb, reinterpret_cast<double2*>(base + w.emb2), p->khat(),
+                              khat_out, p->f64 ? p->khat64() : nullptr, s));
+  p->gram_done = true;
+  return RECON_OK;
 }
 
 const char* recon_status_string(recon_status_t s) {

@@ -221,4 +221,31 @@ hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const 
 hipError_t launch_adjoint_f64(int64_t M, int N, int B, const double2* ph, const float2* y,
                               double2* b, double2* part, hipStream_t s);
 
+// ---- convolution gridding / non-uniform FFT (Sections 1, 4.1, 5) -----------
+// Per-sample Kaiser-Bessel weights wy, wx [M][W], footprint origins base
+// [M] (mod G) and sample phases pf [M] (exp(-i 2 pi (kx + ky) h) or 1).
+hipError_t launch_grid_weights(int64_t M, int G, int W, double beta, int h, int phase,
+                               const double* k, int2* base, double* wy, double* wx, double2* pf,
+                               hipStream_t s);
+// grid[f][G][G] = spread of c = scale * w * pf * y[f] (y != NULL, B frames) or
+// of c = scale * w (y == NULL, one grid); toff/tent: per-tile sample lists.
+hipError_t launch_grid_spread(int G, int W, int B, int64_t M, const int* toff, const int* tent,
+                              const int2* base, const double* wy, const double* wx,
+                              const double2* pf, const float2* y, const double* w, double scale,
+                              double2* grid, hipStream_t s);
+// out[f][n][m] = FFT2(grid[f])[(n-h) mod G][(m-h) mod G] * deap[n] * deap[m].
+hipError_t launch_grid_fft(int G, int Nout, int h, int B, const double2* grid, double2* rows,
+                           const double* deap, float2* out, const double2* tw, hipStream_t s);
+hipError_t launch_grid_fft(int G, int Nout, int h, int B, const double2* grid, double2* rows,
+                           const double* deap, double2* out, const double2* tw, hipStream_t s);
+// w[l] <- w[l] / Re(interpolation of grid at sample l) * scale.
+hipError_t launch_dcf_update(int G, int W, int64_t M, const int2* base, const double* wy,
+                             const double* wx, const double2* grid, double* w, double scale,
+                             hipStream_t s);
+hipError_t launch_fill_f64(size_t n, double v, double* p, hipStream_t s);
+// Circular L x L embedding of the lags |a|, |b| <= N-1 of a 2N x 2N type-1
+// output (lag a at row a + N), optional export [2N-1][2N-1] complex128.
+hipError_t launch_lag_embed(int N, int L, const double2* lag2n, double* lag_out, double2* emb,
+                            hipStream_t s);
+
 }  // namespace recon

@@ -69,6 +69,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_solve_hq": (i32, [vp, vp, i32, f64, f64, i32, i32, i32, vp, i32, vp, sz, vp,
                                  vp]),
         "recon_solve_hq_iterate": (i32, [vp, i32, i32, vp, sz, vp]),
+        "recon_grid_bytes": (sz, [i64, i32, i32, i32]),
+        "recon_grid_plan": (i32, [vp, i64, i32, i32, i32, f64, vp, sz, vp, c.POINTER(vp)]),
+        "recon_grid_info": (i32, [vp, c.POINTER(i32), c.POINTER(i32), c.POINTER(f64)]),
+        "recon_grid_destroy": (None, [vp]),
+        "recon_grid_workspace_bytes": (sz, [vp, i32]),
+        "recon_grid_adjoint": (i32, [vp, vp, vp, i32, vp, vp, sz, vp]),
+        "recon_grid_density": (i32, [vp, i32, vp, vp, sz, vp]),
+        "recon_gram_nufft_workspace_bytes": (sz, [i64, i32, i32, i32]),
+        "recon_gram_kernel_nufft": (i32, [vp, i32, vp, sz, vp, vp, vp]),
         "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
         "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, f64, f64, i32, vp, sz, vp]),
         "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
@@ -174,6 +183,24 @@ class Plan:
         lag = (torch.empty((2 * self.N - 1, 2 * self.N - 1), dtype=torch.complex128, device="cuda")
                if want_lag else None)
         _check(lib.recon_gram_kernel(self._h, ws.data_ptr(), n, _ptr(khat), _ptr(lag), _stream()))
+        torch.cuda.current_stream().synchronize()
+        del ws
+        return khat, lag
+
+    def gram_kernel_nufft(self, W: int = 11, want_khat: bool = False, want_lag: bool = False):
+        """The Gram kernel with its lag kernel from a Kaiser-Bessel non-uniform
+        FFT of width W instead of the exact sums."""
+        import torch
+        lib = load()
+        n = lib.recon_gram_nufft_workspace_bytes(self.M, self.N, self.L, int(W))
+        if n == 0:
+            raise ReconError(E_RANGE, "invalid NUFFT Gram geometry")
+        ws = _dev_buf(n)
+        khat = torch.empty((self.L, self.L), dtype=torch.float32, device="cuda") if want_khat else None
+        lag = (torch.empty((2 * self.N - 1, 2 * self.N - 1), dtype=torch.complex128, device="cuda")
+               if want_lag else None)
+        _check(lib.recon_gram_kernel_nufft(self._h, int(W), ws.data_ptr(), n, _ptr(khat),
+                                           _ptr(lag), _stream()))
         torch.cuda.current_stream().synchronize()
         del ws
         return khat, lag
@@ -303,6 +330,63 @@ class Plan:
         _check(load().recon_solve_end(self._h, x.data_ptr(), st.data_ptr(), ws.data_ptr(), n,
                                       _stream()))
         return x, stats_to_numpy(st, B)
+
+
+class GridPlan:
+    """Kaiser-Bessel convolution gridding on an N x N output (grid G, kernel
+    width W): the density-weighted gridding reconstruction and the NUFFT form
+    of A^H y."""
+
+    def __init__(self, k: np.ndarray, N: int, G: int = 0, W: int = 7, beta: float = 0.0):
+        lib = load()
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+        self.M = int(k.shape[0])
+        self.N = int(N)
+        nbytes = lib.recon_grid_bytes(self.M, self.N, int(G), int(W))
+        if nbytes == 0:
+            raise ReconError(E_RANGE, "invalid grid geometry")
+        self.mem = _dev_buf(nbytes)
+        h = ctypes.c_void_p()
+        _check(lib.recon_grid_plan(k.ctypes.data, self.M, self.N, int(G), int(W), float(beta),
+                                   self.mem.data_ptr(), nbytes, _stream(), ctypes.byref(h)))
+        self._h = h
+        g, w, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib.recon_grid_info(h, ctypes.byref(g), ctypes.byref(w), ctypes.byref(b)))
+        self.G, self.W, self.beta = g.value, w.value, b.value
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.recon_grid_destroy(h)
+            self._h = None
+
+    def workspace(self, B: int):
+        if B not in self._ws:
+            n = load().recon_grid_workspace_bytes(self._h, B)
+            self._ws[B] = (_dev_buf(n), n)
+        return self._ws[B]
+
+    def adjoint(self, y, w=None):
+        """(1/N) sum_l w_l y_l exp(-i 2 pi (kx m + ky n)) for each frame of y
+        (device complex64 [B][M]); w: device float64 [M] or None."""
+        import torch
+        y = y.contiguous()
+        B = y.shape[0]
+        out = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
+        ws, n = self.workspace(B)
+        _check(load().recon_grid_adjoint(self._h, y.data_ptr(), _ptr(w), B, out.data_ptr(),
+                                         ws.data_ptr(), n, _stream()))
+        return out
+
+    def density(self, iters: int = 20):
+        """Pipe-Menon density-compensation weights (device float64 [M])."""
+        import torch
+        w = torch.empty(self.M, dtype=torch.float64, device="cuda")
+        ws, n = self.workspace(1)
+        _check(load().recon_grid_density(self._h, int(iters), w.data_ptr(), ws.data_ptr(), n,
+                                         _stream()))
+        return w
 
 
 class Pool:
