@@ -186,6 +186,22 @@ recon_status_t recon_gram_apply(recon_plan_t plan, const float* v, int32_t B,
                                 float* Qv, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Gram apply as recon_gram_apply, with its row-transform intermediate in a
+ * fixed 64 MiB device array inside the library instead of a caller
+ * workspace.  Nothing is allocated by the call: each GPU the library runs on
+ * holds its own copy of the array until the process ends (its address is
+ * looked up on the first call on a device).  B * N * L * 8 bytes must not
+ * exceed recon_gram_apply_noalloc_max_bytes() (64 MiB; RECON_E_RANGE
+ * otherwise, before anything is launched).  The caller still provides v and
+ * Qv.  All calls on one GPU share the array, so calls that overlap on one
+ * GPU (different streams, or threads without ordering) race; calls on one
+ * stream are ordered and safe. */
+size_t recon_gram_apply_noalloc_max_bytes(void);
+recon_status_t recon_gram_apply_noalloc(recon_plan_t plan, const float* v, int32_t B, float* Qv,
+                                        void* stream);
+
 /* ---- solver ------------------------------------------------------------- */
 
 /* Section 3.3: minimise ||y - A x||^2 + lambda sum phi(|D x|) for B frames

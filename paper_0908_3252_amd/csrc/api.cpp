@@ -742,6 +742,54 @@ recon_status_t recon_gram_apply(recon_plan_t p, const float* v, int32_t B, float
                     w.img(w.lay.T), nullptr, as_stream(stream));
 }
 
+// ---- allocation-free Gram apply --------------------------------------------
+// The row-pass intermediate of recon_gram_apply_noalloc lives in this
+// file-scope device array (one copy per GPU, for the life of the process).
+// Host code never uses its name as an address: the device address is taken
+// once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array (looked up on first use).
+static recon_status_t scratch_on_current_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RECON_E_RANGE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(RECON_E_HIP, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RECON_OK;
+}
+
+extern "C" size_t recon_gram_apply_noalloc_max_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+extern "C" recon_status_t recon_gram_apply_noalloc(recon_plan_t p, const float* v, int32_t B,
+                                                   float* Qv, void* stream) {
+  g_last_error.clear();
+  if (!p || !v || !Qv) return fail(RECON_E_ARG, "NULL argument");
+  if (v == Qv) return fail(RECON_E_ARG, "v and Qv may not alias");
+  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
+  const size_t need = (size_t)B * p->N * p->L * sizeof(float2);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(RECON_E_RANGE, "B * N * L * 8 bytes exceeds the 64 MiB scratch of "
+                               "recon_gram_apply_noalloc (use fewer frames per call)");
+  void* T = nullptr;
+  recon_status_t st = scratch_on_current_device(&T);
+  if (st != RECON_OK) return st;
+  return gram_apply(p, reinterpret_cast<const float2*>(v), reinterpret_cast<float2*>(Qv), B,
+                    static_cast<float2*>(T), nullptr, as_stream(stream));
+}
+
 // lambda0 >= 0 and, when it is > 0, alpha0 > 0 (the background term).
 static recon_status_t check_background(double lambda0, double alpha0) {
   if (!(lambda0 >= 0.0) || !std::isfinite(lambda0)) return fail(RECON_E_RANGE, "lambda0 must be >= 0");

@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_grid_density": (i32, [vp, i32, vp, vp, sz, vp]),
         "recon_gram_nufft_workspace_bytes": (sz, [i64, i32, i32, i32]),
         "recon_gram_kernel_nufft": (i32, [vp, i32, vp, sz, vp, vp, vp]),
+        "recon_gram_apply_noalloc_max_bytes": (sz, []),
+        "recon_gram_apply_noalloc": (i32, [vp, vp, i32, vp, vp]),
         "recon_pool_reset": (i32, [vp, i32, i32, vp, sz, vp]),
         "recon_pool_admit": (i32, [vp, i32, vp, f64, f64, f64, f64, i32, vp, sz, vp]),
         "recon_pool_step": (i32, [vp, i32, vp, sz, vp]),
