@@ -194,6 +194,221 @@ def cpu_baseline(args, torch, recon, prec):
                 seconds=dt), rel, (y[0], xo)
 
 
+def cuda_ms(torch, fn, reps=3):
+    """Median duration (ms) of fn() on the current stream (HIP events), after
+    one untimed call."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+SERIES_FRAMES = (0, 42, 85, 127)
+
+
+def _rel(torch, a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def extra_precision_form(c):
+    """The precision form on the 128-frame series: FP32 and split BF16 / FP16
+    x3 NUDFT contractions with the FP32 iteration (and the FP64 adjoint with
+    the FP32 iteration), one whole step each (plan, Gram kernel, adjoint,
+    iterations, forward model) in calls of 64 frames (these plans take at
+    most 64 frames per call), against the FP64-iteration result of the main
+    benchmark on frames 0, 42, 85, 127 (the parity tests hold that result to
+    the FP64 oracle at 2.5e-8)."""
+    torch, recon, lib = c["torch"], c["recon"], c["lib"]
+    B, N, L, M, iters = c["B"], c["N"], c["L"], c["M"], c["iters"]
+    y, xref = c["y"], c["x"]
+    res = {}
+    for name, prec in (("fp64_adjoint_fp32_iteration", recon.FP64), ("fp32", recon.FP32),
+                       ("fp16x3", recon.FP16X3), ("bf16x3", recon.BF16X3)):
+        plan = recon.Plan(c["k_host"], N, L, prec=prec)
+        plan.gram_kernel()
+        G = min(B, 64)
+        ws, wsn = plan.workspace(G)
+        pbytes = lib.recon_plan_bytes(M, N, L, prec)
+        gws_n = lib.recon_gram_workspace_bytes(M, N, L)
+        gws = torch.empty(gws_n, dtype=torch.uint8, device="cuda")
+        xo = torch.empty((B, N, N), dtype=torch.complex64, device="cuda")
+        yfit = torch.empty((B, M), dtype=torch.complex64, device="cuda")
+        import ctypes
+
+        def step():
+            h = ctypes.c_void_p()
+            recon._check(lib.recon_plan(c["k_host"].ctypes.data, M, N, L, prec,
+                                        plan.mem.data_ptr(), pbytes, c["stream"], ctypes.byref(h)))
+            try:
+                recon._check(lib.recon_gram_kernel(h, gws.data_ptr(), gws_n, None, None,
+                                                   c["stream"]))
+                for f0 in range(0, B, G):
+                    g = min(G, B - f0)
+                    recon._check(lib.recon_solve(h, y[f0].data_ptr(), g, c["lam"], c["delta"],
+                                                 iters, 0, xo[f0].data_ptr(), 0, ws.data_ptr(),
+                                                 wsn, None, c["stream"]))
+                    recon._check(lib.recon_forward(h, xo[f0].data_ptr(), g, yfit[f0].data_ptr(),
+                                                   ws.data_ptr(), wsn, c["stream"]))
+            finally:
+                lib.recon_plan_destroy(h)
+
+        ms = cuda_ms(torch, step, reps=3)
+        errs = {f"f{f}": _rel(torch, xo[f], xref[f]) for f in SERIES_FRAMES if f < B}
+        res[name] = {"recons_per_sec": round(B / (ms * 1e-3), 2), "ms_per_step": round(ms, 3),
+                     "calls_per_step": -(-B // G),
+                     "rel_l2_vs_fp64_iteration": {k: float(f"{v:.3e}") for k, v in errs.items()},
+                     "meets_1e-4": bool(max(errs.values()) < 1e-4)}
+        del plan, ws, gws, xo, yfit
+    return res
+
+
+def extra_half_quadratic(c):
+    """Section 5's half-quadratic alternative against the pseudo-CG on the
+    128-frame batch (FP64 iteration): criterion J (median over frames) and
+    time for the same numbers of Gram applications."""
+    torch, recon = c["torch"], c["recon"]
+    B, N, L = c["B"], c["N"], c["L"]
+    plan = recon.Plan(c["k_host"], N, L, prec=recon.FP64_ITER64)
+    plan.gram_kernel()
+    y = c["y"]
+    rows = []
+    xs = {}
+    for apps in (60, 150, 300):
+        out = {"gram_applications": apps}
+        res = {}
+        ms = cuda_ms(torch, lambda: res.__setitem__("cg", plan.solve(y, c["lam"], c["delta"],
+                                                                     apps)), reps=1)
+        out["cg"] = {"ms": round(ms, 2), "J_median": float(np.median(res["cg"][1]["J"]))}
+        outer = apps // 10
+        ms = cuda_ms(torch, lambda: res.__setitem__("hq", plan.solve_hq(y, c["lam"], c["delta"],
+                                                                        outer, 10)), reps=1)
+        out["half_quadratic"] = {"outer": outer, "inner": 10, "ms": round(ms, 2),
+                                 "J_median": float(np.median(res["hq"][1]["J"]))}
+        out["J_hq_minus_J_cg_median"] = float(np.median(res["hq"][1]["J"] - res["cg"][1]["J"]))
+        xs[apps] = (res["cg"][0], res["hq"][0])
+        rows.append(out)
+    cg300, hq300 = xs[300]
+    return {"frames": B, "iteration": "fp64", "runs": rows,
+            "rel_l2_hq_vs_cg_at_300_median": float(np.median(
+                [_rel(torch, hq300[f], cg300[f]) for f in range(0, B, 16)]))}
+
+
+def extra_gridding(c):
+    """The paper's comparison (Section 4.1): Kaiser-Bessel gridding (W = 7,
+    grid 2N, Pipe-Menon density weights) against the regularised
+    reconstruction (the benchmark's FP64-iteration result), quadratic error
+    in ROI1 (central square) and variance in ROI2 (a flat region) against
+    the synthetic truth, on 8 frames."""
+    torch, recon = c["torch"], c["recon"]
+    prob, y, x, B, N = c["prob"], c["y"], c["x"], c["B"], c["N"]
+    gp = recon.GridPlan(c["k_host"], N, W=7)
+    box = {}
+    ms_dcf = cuda_ms(torch, lambda: box.__setitem__("w", gp.density(10)), reps=1)
+    w = box["w"]
+    ms_grid = cuda_ms(torch, lambda: box.__setitem__("img", gp.adjoint(y, w)), reps=3)
+    img = box["img"]
+    frames = list(range(0, B, max(1, B // 8)))[:8]
+    q_g, q_r, v_g, v_r = [], [], [], []
+    for f in frames:
+        xt = prob.x_true[f]
+        roi1, roi2 = synthetic.roi_masks(xt)
+        xg = img[f].cpu().numpy().astype(np.complex128)
+        xr = x[f].cpu().numpy().astype(np.complex128)
+        for arr, q, v in ((xg, q_g, v_g), (xr, q_r, v_r)):
+            q.append(float(np.mean(np.abs(arr - xt)[roi1] ** 2)))
+            vals = arr[roi2]
+            v.append(float(np.mean(np.abs(vals - vals.mean()) ** 2)))
+    return {"kernel_width": 7, "grid": gp.G, "beta": round(gp.beta, 4),
+            "density_iterations": 10, "density_ms": round(ms_dcf, 3),
+            "gridding_ms_per_batch": round(ms_grid, 3), "frames": B,
+            "frames_scored": len(frames),
+            "roi1_quadratic_error": {"gridding_median": float(np.median(q_g)),
+                                     "regularised_median": float(np.median(q_r)),
+                                     "ratio_median": float(np.median(np.array(q_g) / np.array(q_r)))},
+            "roi2_variance": {"gridding_median": float(np.median(v_g)),
+                              "regularised_median": float(np.median(v_r)),
+                              "ratio_median": float(np.median(np.array(v_g) / np.array(v_r)))}}
+
+
+def extra_nufft(c):
+    """Section 5's NUFFT precomputation (Kaiser-Bessel, W = 11, grid 2N for
+    D = A^H y, 4N for the lag kernel) against the exact FP64-accumulated
+    sums: time per 128-frame batch, relative difference, and one 256^2 frame
+    solved with the FP64 iteration from the NUFFT D and spectrum against the
+    oracle (exact sums)."""
+    torch, recon = c["torch"], c["recon"]
+    B, N, L, y = c["B"], c["N"], c["L"], c["y"]
+    W = 11
+    gp = recon.GridPlan(c["k_host"], N, W=W)
+    exact = recon.Plan(c["k_host"], N, L, prec=recon.FP64_ITER64)
+    box = {}
+    ms_exact_b = cuda_ms(torch, lambda: box.__setitem__("be", exact.adjoint(y)), reps=3)
+    ms_nufft_b = cuda_ms(torch, lambda: box.__setitem__("bn", gp.adjoint(y)), reps=3)
+    eb = float(np.median([_rel(torch, box["bn"][f], box["be"][f]) for f in range(0, B, 8)]))
+    ms_exact_g = cuda_ms(torch, lambda: exact.gram_kernel(), reps=3)
+    nplan = recon.Plan(c["k_host"], N, L, prec=recon.FP64_ITER64)
+    ms_nufft_g = cuda_ms(torch, lambda: nplan.gram_kernel_nufft(W), reps=3)
+    _, lag_e = exact.gram_kernel(want_lag=True)
+    _, lag_n = nplan.gram_kernel_nufft(W, want_lag=True)
+    eg = _rel(torch, lag_n, lag_e)
+    out = {"kernel_width": W, "grid_for_D": gp.G, "beta": round(gp.beta, 4),
+           "stated_bound": float(f"{4.0 / float(np.i0(gp.beta)):.2e}"),
+           "D_batch_ms": {"exact_fp64": round(ms_exact_b, 3), "nufft": round(ms_nufft_b, 3)},
+           "D_rel_diff_median": float(f"{eb:.3e}"),
+           "gram_kernel_ms": {"exact_fp64": round(ms_exact_g, 3),
+                              "nufft_incl_host_binning": round(ms_nufft_g, 3)},
+           "lag_kernel_rel_diff": float(f"{eg:.3e}")}
+    of = c.get("oracle_frame")
+    if of is not None:
+        y0, xo = of
+        yd = torch.from_numpy(np.ascontiguousarray(y0[None], dtype=np.complex64)).cuda()
+        pgp = recon.GridPlan(c["k_host"], N, W=W)
+        b0 = pgp.adjoint(yd)
+        nplan.begin(b=b0, lam=c["lam"], delta=c["delta"])
+        nplan.iterate(c["iters"])
+        xg, _ = nplan.end()
+        xg = xg[0].cpu().numpy().astype(np.complex128)
+        out["frame0_rel_l2_vs_oracle_exact_sums"] = float(
+            f"{np.linalg.norm(xg - xo) / np.linalg.norm(xo):.3e}")
+    return out
+
+
+def extra_served_mixed(args, c):
+    """The mixed-size served stream (N in {64..384}, 8/16/32 interleaves,
+    Poisson arrivals) at the given rates, FP64 iteration and the precision
+    forms (FP32, split FP16 / BF16 x3 with the FP32 iteration), each result
+    compared with the FP64-iteration result of the same request."""
+    from paper_0908_3252_amd import serving as srv
+    wl = srv.make_workload(args.mixed_count, 4)
+    runs = []
+    for rate in [float(v) for v in args.mixed_rates.split(",")]:
+        ref = None
+        for prec in ("fp64i", "fp32", "fp16x3", "bf16x3"):
+            if prec == "fp64i":
+                o, ref = srv.serve(rate, wl, prec=prec, keep_results=True, verify=1)
+            else:
+                o = srv.serve(rate, wl, prec=prec, reference=ref, verify=1)
+            keep = {k: o[k] for k in ("rate", "prec", "requests", "completed", "recons_per_sec",
+                                      "p50_ms", "p99_ms", "status_ok", "bitwise_equal_standalone",
+                                      "rel_l2_vs_reference") if k in o}
+            for k in ("recons_per_sec", "p50_ms", "p99_ms"):
+                if k in keep:
+                    keep[k] = round(keep[k], 2)
+            runs.append(keep)
+            log(f"mixed {rate}/s {prec}: {keep}")
+        ref = None
+    return {"requests_per_rate": args.mixed_count, "runs": runs,
+            "what": "arrival-to-result latency, first 10% excluded; rel_l2_vs_reference: each "
+                    "result against the FP64-iteration result of the same request"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +433,12 @@ def main():
     ap.add_argument("--criterion", default="plain", choices=["plain", "full"],
                     help="plain: hyperbolic difference penalty (the workload's criterion); "
                          "full: the paper's criterion, Huber differences + background penalty")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision form, half-quadratic, gridding, NUFFT and mixed "
+                         "serving sections (profiling runs)")
+    ap.add_argument("--mixed-count", type=int, default=600,
+                    help="requests per rate of the mixed-size served stream (0: off)")
+    ap.add_argument("--mixed-rates", default="200,2000")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(reference kernel for scaling hardware byte counters)")
@@ -343,6 +564,10 @@ def main():
             ach = kb / (avg_ms * 1e-3) / 1e9
             ent.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                        frac=round(ach / HBM_PEAK_GBS, 4), algorithmic_bytes_per_launch=kb)
+            # the same launch priced with complex64 elements (8 bytes), the
+            # byte model of the FP32 iteration
+            kb8 = kernel_bytes(k, N, L, B, 8)
+            ent["frac_complex64_model"] = round(kb8 / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             if k == "colpass":
                 fl = kernel_flops(k, N, M, L, B)
                 vt = "fp64" if es == 16 else "fp32"
@@ -355,6 +580,20 @@ def main():
     dominant = max(rooflines, key=lambda k: rooflines[k]["ms_per_step"])
     roofline = dict(rooflines[dominant])
     roofline["kernel"] = dominant
+    roofline["basis"] = (f"algorithmic bytes with {es}-byte complex elements (the element size "
+                         f"this iteration stores); frac_complex64_model prices the same launch "
+                         f"with 8-byte elements")
+    # one whole iteration (direction + column pass + update) against the
+    # 176 N^2 bytes-per-frame model of the FP32 iteration
+    it_ms = sum(rooflines[k]["avg_launch_ms"] for k in ("dir_rowfft", "colpass", "update")
+                if k in rooflines)
+    iteration_model = None
+    if it_ms > 0:
+        mb = 176.0 * N * N * B
+        iteration_model = {"ms_per_iteration": round(it_ms, 5), "model_bytes": mb,
+                           "frac_of_hbm_peak": round(mb / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "what": "176 N^2 bytes per frame and iteration (complex64 state: "
+                                   "Toeplitz apply 80 N^2 + stencil and updates 96 N^2)"}
 
     # single-frame latency (one 256^2 reconstruction, same hot path, B = 1)
     lat = []
@@ -486,6 +725,7 @@ def main():
                                     "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "roofline": roofline,
         "rooflines": rooflines,
+        "iteration_model": iteration_model,
         "csrc_digest": digest,
         "status_ok_frames": int(np.sum(st["status"] == 0)),
         "grad_ratio_median": float(np.median(st["grad_ratio"])),
@@ -497,6 +737,19 @@ def main():
         out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
         if rel is not None:
             out["rel_l2_vs_oracle_one_frame"] = rel
+    if not args.no_extras and args.workload == "series256" and args.criterion == "plain":
+        ctx = dict(torch=torch, recon=recon, lib=lib, prob=prob, y=y, x=x, B=B, N=N, L=L, M=M,
+                   iters=iters, k_host=k_host, lam=c_lam, delta=c_delta, stream=stream,
+                   oracle_frame=oracle_frame)
+        for name, fn in (("precision_form", extra_precision_form),
+                         ("half_quadratic_vs_cg", extra_half_quadratic),
+                         ("gridding_comparison", extra_gridding),
+                         ("nufft_precompute", extra_nufft)):
+            log(f"extra: {name}")
+            out[name] = fn(ctx)
+        if args.mixed_count > 0:
+            log("extra: mixed-size served stream")
+            out["served_mixed"] = extra_served_mixed(args, ctx)
     print(json.dumps(out), flush=True)
 
 
