@@ -9,7 +9,8 @@
 // rows are produced along columns):
 //   row pass      v[N][N]  -> T[N][L]      (row FFTs, first half of inputs zero)
 //   column pass   T[N][L]  -> T[N][L]      (column FFT, x khat, column IFFT,
-//                                           in place, tiles staged in LDS)
+//                                           in place, tiles staged in LDS
+//                                           except for FP64 at L = 512)
 //   row inverse   T[N][L]  -> Qv[N][N]     (row IFFTs, first N outputs kept)
 // Inside the iteration the row passes are fused with the conjugate-gradient
 // direction and update kernels (iterate.hip); the <d, Qd> partial is taken
@@ -64,11 +65,20 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
 template <int L, int ES = 1>
 struct ColCfg {
   static constexpr int T = FftShape<L>::T;
-  static constexpr int THREADS = ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
+  // DIRECT (FP64 at L = 512): no staging tile; each team reads and writes
+  // its column straight from global memory, four adjacent columns per block
+  // (the two blocks that share a 128-byte row segment are mapped to one
+  // XCD), twiddles in registers.  That leaves 138 registers and 18 KB of LDS
+  // and takes the LDS twiddle reads and the tile round trip off the LDS pipe,
+  // which bounds the FP64 transform (0.189 -> 0.179 ms per 128-frame launch;
+  // the same without register twiddles, at 84 registers and 5 waves per
+  // SIMD, was no faster than the staged form).
+  static constexpr bool DIRECT = (L == 512 && ES == 2);
+  static constexpr int THREADS = DIRECT ? 256 : ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
   // (FP64 at L >= 1024 keeps 8 columns: 128-byte row segments, whole cache
   // lines; that form is register-bound to one block per CU anyway)
-  static constexpr int COLS = (L >= 1024 && ES == 2) ? 8
+  static constexpr int COLS = DIRECT ? 4 : (L >= 1024 && ES == 2) ? 8
                               : ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
   static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
 };
@@ -93,15 +103,17 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   // INCOL (FP64, wave-local teams): while a team transforms its column, the
   // column's values are in registers, so the column itself (TS >= the
   // component-wise exchange buffer) serves as the team's exchange buffer.
-  constexpr bool INCOL = sizeof(C) == 16 && FftSync<L>::WAVE_LOCAL;
+  constexpr bool DIRECT = CC::DIRECT;
+  constexpr bool INCOL = !DIRECT && sizeof(C) == 16 && FftSync<L>::WAVE_LOCAL;
   constexpr int TS0 = L / 2 + 2;
   constexpr int TS = (INCOL && fft_team_lds<L, C>() > TS0)
                          ? (fft_team_lds<L, C>() + 15) / 16 * 16 + 2 : TS0;
   constexpr int NBUF = INCOL ? 1 : TEAMS * fft_team_lds<L, C>();
-  // FP32 at L <= 512: twiddles in registers (TwRegs) instead of an LDS table
-  constexpr bool TWR = sizeof(C) == 8 && L <= 512;
+  // FP32 at L <= 512 and the DIRECT form: twiddles in registers (TwRegs)
+  // instead of an LDS table
+  constexpr bool TWR = (sizeof(C) == 8 || DIRECT) && L <= 512;
   __shared__ C tw[TWR ? 1 : L];
-  __shared__ C tile[COLS * TS];
+  __shared__ C tile[DIRECT ? 1 : COLS * TS];
   __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
@@ -121,23 +133,27 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   double dqd = 0.0;
   // Stage the block's columns: every load of a thread is issued before the
   // first LDS store (static count: N <= L/2).
-  constexpr int SMAX = (L / 2) * COLS / NT;
+  constexpr int SMAX = DIRECT ? 1 : (L / 2) * COLS / NT;
   C stg[SMAX];
+  if constexpr (!DIRECT) {
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s) {
-    const int i = threadIdx.x + s * NT;
-    const int n = i / COLS, c = i - n * COLS;
-    stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
+    for (int s = 0; s < SMAX; ++s) {
+      const int i = threadIdx.x + s * NT;
+      const int n = i / COLS, c = i - n * COLS;
+      stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
+    }
   }
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   TwRegs<(TWR ? L : 64), C> twr;
   if constexpr (TWR) twr.load(twg, t);
   else load_twiddles<L>(tw, twg);
+  if constexpr (!DIRECT) {
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s) {
-    const int i = threadIdx.x + s * NT;
-    const int n = i / COLS, c = i - n * COLS;
-    if (n < N) tile[c * TS + n] = stg[s];
+    for (int s = 0; s < SMAX; ++s) {
+      const int i = threadIdx.x + s * NT;
+      const int n = i / COLS, c = i - n * COLS;
+      if (n < N) tile[c * TS + n] = stg[s];
+    }
   }
   __syncthreads();
   C* tb = INCOL ? nullptr : team_buf<L>(bufs, team);
@@ -154,7 +170,8 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 #pragma unroll
     for (int e = 0; e < S::V / 2; ++e) {
       const int p = t + e * S::T;
-      val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
+      if constexpr (DIRECT) val[e] = (active && p < N) ? Tf[(size_t)p * L + q0 + c] : cmk<C>(0, 0);
+      else val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
     // the column's kernel values are loaded before the transform, so that
     // their latency is hidden behind it
@@ -180,17 +197,22 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 #pragma unroll
       for (int e = 0; e < S::V / 2; ++e) {
         const int p = t + e * S::T;
-        if (p < N) tile[c * TS + p] = val[e];
+        if (p < N) {
+          if constexpr (DIRECT) Tf[(size_t)p * L + q0 + c] = val[e];
+          else tile[c * TS + p] = val[e];
+        }
       }
     }
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
   }
   __syncthreads();
+  if constexpr (!DIRECT) {
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s) {
-    const int i = threadIdx.x + s * NT;
-    const int n = i / COLS, c = i - n * COLS;
-    if (n < N) Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
+    for (int s = 0; s < SMAX; ++s) {
+      const int i = threadIdx.x + s * NT;
+      const int n = i / COLS, c = i - n * COLS;
+      if (n < N) Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
+    }
   }
   if (p3) {
     double v1[1] = {dqd};
