@@ -13,6 +13,25 @@ from __future__ import annotations
 import argparse
 import collections
 import csv
+import re
+
+
+def short_name(name: str) -> str:
+    """Kernel name without return type and argument list, with the HIP
+    vector types written as float2 / double2."""
+    name = name.replace("HIP_vector_type<double, 2u>", "double2")
+    name = name.replace("HIP_vector_type<float, 2u>", "float2")
+    name = re.sub(r"^void ", "", name)
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    return name[:cut]
 
 
 def _int(row, *names):
@@ -32,7 +51,7 @@ def summarize(path: str):
                       _int(r, "Grid_Size_Z"))
         wx, wy, wz = max(wx, 1), max(wy, 1), max(wz, 1)
         shape = f"{gx // wx}x{max(gy, 1) // wy}x{max(gz, 1) // wz}"
-        groups[(r["Kernel_Name"], shape, wx * wy * wz)].append(dur)
+        groups[(short_name(r["Kernel_Name"]), shape, wx * wy * wz)].append(dur)
     total = sum(sum(v) for v in groups.values()) or 1.0
     rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
     return rows, total
