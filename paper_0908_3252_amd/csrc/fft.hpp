@@ -154,6 +154,36 @@ struct IsTwRegs<TwRegs<L, C>> {
   static constexpr bool value = true;
 };
 
+// One twiddle per radix-8 pass in registers (V = 8): W^k of the thread's
+// butterfly; the pass multiplies input r by W^{rk}, formed as the running
+// product W^{(r-1)k} W^k, so that a single product is live at a time.  That
+// needs a third of TwRegs' registers and none of the seven-entry array, at
+// up to six roundings per power instead of two (used in FP64, where that
+// is ~1e-15).
+template <int L, typename C>
+struct TwPow {
+  using S = FftShape<L>;
+  static_assert(S::V == 8, "one butterfly per radix-8 pass");
+  static constexpr int NPT = S::NP - 1;
+  C w[NPT > 0 ? NPT : 1];
+  __device__ __forceinline__ void load(const C* __restrict__ g, int t) {
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+      const int ns = S::S0 << (3 * p);  // span of pass p + 1
+      w[p] = g[(t & (ns - 1)) * (L / (8 * ns))];
+    }
+  }
+};
+
+template <typename T>
+struct IsTwPow {
+  static constexpr bool value = false;
+};
+template <int L, typename C>
+struct IsTwPow<TwPow<L, C>> {
+  static constexpr bool value = true;
+};
+
 // The seven twiddles W^{rk}, r = 1..7, of pass P from TwRegs.
 template <int P, int L, typename C>
 __device__ __forceinline__ void twiddles7(const TwRegs<L, C>& tw, C (&w)[7]) {
@@ -181,7 +211,16 @@ __device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const TW
     C a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
-    if constexpr (NS > 1 && IsTwRegs<TW>::value) {
+    if constexpr (NS > 1 && IsTwPow<TW>::value) {
+      C w1 = tw.w[P - 1];
+      if (INV) w1.y = -w1.y;
+      C w = w1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        a[r] = c_mul(a[r], w);
+        if (r + 1 < R) w = c_mul(w, w1);
+      }
+    } else if constexpr (NS > 1 && IsTwRegs<TW>::value) {
       C w7[7];
       twiddles7<P>(tw, w7);
 #pragma unroll
@@ -300,7 +339,7 @@ __device__ __forceinline__ void fft_passes(C (&v)[FftShape<L>::V], int t, C* tb,
 // (block barriers); for L <= 512 only the team's own wavefront is involved.
 // tb: this team's exchange buffers (fft_team_lds<L, C>() elements of LDS);
 // tw: the per-pass LDS twiddle table built by load_twiddles (a pointer), or
-// the thread's TwRegs.
+// the thread's TwRegs or TwPow.
 template <int L, bool INV, bool HALF_IN, typename C, typename TW>
 __device__ __forceinline__ void fft_team(C (&v)[FftShape<L>::V], int t, C* tb, const TW& tw) {
   if (HALF_IN) {

@@ -9,8 +9,7 @@
 // rows are produced along columns):
 //   row pass      v[N][N]  -> T[N][L]      (row FFTs, first half of inputs zero)
 //   column pass   T[N][L]  -> T[N][L]      (column FFT, x khat, column IFFT,
-//                                           in place, tiles staged in LDS
-//                                           except for FP64 at L = 512)
+//                                           in place, tiles staged in LDS)
 //   row inverse   T[N][L]  -> Qv[N][N]     (row IFFTs, first N outputs kept)
 // Inside the iteration the row passes are fused with the conjugate-gradient
 // direction and update kernels (iterate.hip); the <d, Qd> partial is taken
@@ -65,20 +64,11 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
 template <int L, int ES = 1>
 struct ColCfg {
   static constexpr int T = FftShape<L>::T;
-  // DIRECT (FP64 at L = 512): no staging tile; each team reads and writes
-  // its column straight from global memory, four adjacent columns per block
-  // (the two blocks that share a 128-byte row segment are mapped to one
-  // XCD), twiddles in registers.  That leaves 138 registers and 18 KB of LDS
-  // and takes the LDS twiddle reads and the tile round trip off the LDS pipe,
-  // which bounds the FP64 transform (0.189 -> 0.179 ms per 128-frame launch;
-  // the same without register twiddles, at 84 registers and 5 waves per
-  // SIMD, was no faster than the staged form).
-  static constexpr bool DIRECT = (L == 512 && ES == 2);
-  static constexpr int THREADS = DIRECT ? 256 : ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
+  static constexpr int THREADS = ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
   // (FP64 at L >= 1024 keeps 8 columns: 128-byte row segments, whole cache
   // lines; that form is register-bound to one block per CU anyway)
-  static constexpr int COLS = DIRECT ? 4 : (L >= 1024 && ES == 2) ? 8
+  static constexpr int COLS = (L >= 1024 && ES == 2) ? 8
                               : ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
   static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
 };
@@ -103,17 +93,15 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   // INCOL (FP64, wave-local teams): while a team transforms its column, the
   // column's values are in registers, so the column itself (TS >= the
   // component-wise exchange buffer) serves as the team's exchange buffer.
-  constexpr bool DIRECT = CC::DIRECT;
-  constexpr bool INCOL = !DIRECT && sizeof(C) == 16 && FftSync<L>::WAVE_LOCAL;
+  constexpr bool INCOL = sizeof(C) == 16 && FftSync<L>::WAVE_LOCAL;
   constexpr int TS0 = L / 2 + 2;
   constexpr int TS = (INCOL && fft_team_lds<L, C>() > TS0)
                          ? (fft_team_lds<L, C>() + 15) / 16 * 16 + 2 : TS0;
   constexpr int NBUF = INCOL ? 1 : TEAMS * fft_team_lds<L, C>();
-  // FP32 at L <= 512 and the DIRECT form: twiddles in registers (TwRegs)
-  // instead of an LDS table
-  constexpr bool TWR = (sizeof(C) == 8 || DIRECT) && L <= 512;
+  // FP32 at L <= 512: twiddles in registers (TwRegs) instead of an LDS table
+  constexpr bool TWR = sizeof(C) == 8 && L <= 512;
   __shared__ C tw[TWR ? 1 : L];
-  __shared__ C tile[DIRECT ? 1 : COLS * TS];
+  __shared__ C tile[COLS * TS];
   __shared__ C bufs[NBUF];
   __shared__ double red[NT / 64];
   const int f = blockIdx.y;
@@ -133,27 +121,23 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   double dqd = 0.0;
   // Stage the block's columns: every load of a thread is issued before the
   // first LDS store (static count: N <= L/2).
-  constexpr int SMAX = DIRECT ? 1 : (L / 2) * COLS / NT;
+  constexpr int SMAX = (L / 2) * COLS / NT;
   C stg[SMAX];
-  if constexpr (!DIRECT) {
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      const int i = threadIdx.x + s * NT;
-      const int n = i / COLS, c = i - n * COLS;
-      stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
-    }
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
+    const int n = i / COLS, c = i - n * COLS;
+    stg[s] = Tf[(n < N ? (size_t)n * L : 0) + q0 + c];
   }
   const int team = threadIdx.x / S::T, t = threadIdx.x % S::T;
   TwRegs<(TWR ? L : 64), C> twr;
   if constexpr (TWR) twr.load(twg, t);
   else load_twiddles<L>(tw, twg);
-  if constexpr (!DIRECT) {
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      const int i = threadIdx.x + s * NT;
-      const int n = i / COLS, c = i - n * COLS;
-      if (n < N) tile[c * TS + n] = stg[s];
-    }
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
+    const int n = i / COLS, c = i - n * COLS;
+    if (n < N) tile[c * TS + n] = stg[s];
   }
   __syncthreads();
   C* tb = INCOL ? nullptr : team_buf<L>(bufs, team);
@@ -170,8 +154,7 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 #pragma unroll
     for (int e = 0; e < S::V / 2; ++e) {
       const int p = t + e * S::T;
-      if constexpr (DIRECT) val[e] = (active && p < N) ? Tf[(size_t)p * L + q0 + c] : cmk<C>(0, 0);
-      else val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
+      val[e] = (active && p < N) ? tile[c * TS + p] : cmk<C>(0, 0);
     }
     // the column's kernel values are loaded before the transform, so that
     // their latency is hidden behind it
@@ -197,25 +180,100 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 #pragma unroll
       for (int e = 0; e < S::V / 2; ++e) {
         const int p = t + e * S::T;
-        if (p < N) {
-          if constexpr (DIRECT) Tf[(size_t)p * L + q0 + c] = val[e];
-          else tile[c * TS + p] = val[e];
-        }
+        if (p < N) tile[c * TS + p] = val[e];
       }
     }
     if constexpr (!FftSync<L>::WAVE_LOCAL) __syncthreads();
   }
   __syncthreads();
-  if constexpr (!DIRECT) {
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      const int i = threadIdx.x + s * NT;
-      const int n = i / COLS, c = i - n * COLS;
-      if (n < N) Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
-    }
+  for (int s = 0; s < SMAX; ++s) {
+    const int i = threadIdx.x + s * NT;
+    const int n = i / COLS, c = i - n * COLS;
+    if (n < N) Tf[(size_t)n * L + q0 + c] = tile[c * TS + n];
   }
   if (p3) {
     double v1[1] = {dqd};
+    block_sum<1>(v1, red);
+    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + bx] = v1[0];
+  }
+}
+
+// FP64 at L = 512.  A block takes four adjacent columns, one wave-local team
+// (64 threads) per column.  The columns' rows are read and written with
+// lanes along the row segments (4 lanes per 64-byte segment, 64 rows per
+// instruction): read one column per lane, the same bytes took 1.6 x as long
+// (125 against 79 us per 128-frame launch with no transform at all).  Each
+// column goes through LDS to and from its team in the team's own exchange
+// buffer (N <= L/2 values fit in it), the only block barriers being the two
+// around the transforms.  Twiddles as running powers (TwPow) bring it to
+// 124 registers without spills, 4 waves per SIMD (3 with TwRegs: 138-174).
+// The two blocks that share a 128-byte row segment are mapped to one XCD.
+constexpr int COLPASS64_COLS = 4;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colpass_f64_512(int N, double2* __restrict__ T,
+                                                         const double* __restrict__ khat_s,
+                                                         double* __restrict__ p3,
+                                                         const double2* __restrict__ twg,
+                                                         const FrameParam* __restrict__ fp,
+                                                         int kit) {
+  constexpr int L = 512;
+  using C = double2;
+  constexpr int COLS = COLPASS64_COLS;
+  // team stride: the exchange buffer plus two elements, so that the four
+  // columns of one row (written by four adjacent lanes) fall in different
+  // LDS banks
+  constexpr int TB = fft_team_lds<L, C>() + 2;
+  static_assert(FftShape<L>::T == 64 && 256 / FftShape<L>::T == COLS, "one team per column");
+  static_assert(TB >= L / 2, "a column fits in its team's buffer");
+  if (fp && kit >= fp[blockIdx.y].stop_at) return;
+  __shared__ C bufs[COLS * TB];
+  __shared__ double red[4];
+  const int f = blockIdx.y;
+  int bx = blockIdx.x;
+  if (gridDim.x % 8 == 0) bx = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int q0 = bx * COLS;
+  C* Tf = T + (size_t)f * N * L;
+  const int team = threadIdx.x / 64, t = threadIdx.x % 64;
+  const int ci = threadIdx.x % COLS, ri = threadIdx.x / COLS;  // staging: column, first row
+  C ld[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int n = ri + 64 * s;
+    ld[s] = n < N ? Tf[(size_t)n * L + q0 + ci] : cmk<C>(0, 0);
+  }
+  TwPow<L, C> tw;
+  tw.load(twg, t);
+  const double* kq = khat_s + (size_t)(q0 + team) * L;
+  double kv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) kv[e] = kq[t + e * 64];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) bufs[ci * TB + ri + 64 * s] = ld[s];
+  __syncthreads();
+  C* tb = bufs + team * TB;
+  C val[8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) val[e] = tb[t + 64 * e];
+  // (the reads above precede the transform's exchange writes within the wave)
+  fft_team<L, false, true>(val, t, tb, tw);
+  double acc = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    acc = fma(kv[e], c_abs2(val[e]), acc);
+    val[e] = c_scale(val[e], kv[e]);
+  }
+  fft_team<L, true, false>(val, t, tb, tw);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) tb[t + 64 * e] = val[e];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int n = ri + 64 * s;
+    if (n < N) Tf[(size_t)n * L + q0 + ci] = bufs[ci * TB + ri + 64 * s];
+  }
+  if (p3) {
+    double v1[1] = {acc};
     block_sum<1>(v1, red);
     if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + bx] = v1[0];
   }
@@ -270,6 +328,7 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
   }
 
 int fft_cols_per_block(int L, bool f64) {
+  if (f64 && L == 512) return COLPASS64_COLS;
   switch (L) {
     case 64: return f64 ? ColCfg<64, 2>::COLS : ColCfg<64>::COLS;
     case 128: return f64 ? ColCfg<128, 2>::COLS : ColCfg<128>::COLS;
@@ -294,6 +353,13 @@ template <typename C>
 static hipError_t colpass_any(int L, int N, int B, C* T, const real_t<C>* khat_s, double* p3,
                               const C* tw, const FrameParam* fp, int k, hipStream_t s) {
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
+  if constexpr (sizeof(C) == 16) {
+    if (L == 512) {
+      if (N > L / 2) return hipErrorInvalidValue;
+      k_colpass_f64_512<<<dim3(L / COLPASS64_COLS, B), 256, 0, s>>>(N, T, khat_s, p3, tw, fp, k);
+      return hipGetLastError();
+    }
+  }
   dim3 grid(L / fft_cols_per_block(L, sizeof(C) == 16), B);
   RECON_L_SWITCH(L, (k_colpass<LL, C><<<grid, ColCfg<LL, sizeof(C) / 8>::THREADS, 0, s>>>(
                         N, T, khat_s, p3, tw, fp, k)));
