@@ -68,10 +68,13 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   // halo element j of a thread: row j / W, column j % W (W a power of two)
   constexpr int HX = (3 * W + 255) / 256;  // x halo elements per thread (3 rows)
   constexpr int HD = (W + 255) / 256;      // r, d halo elements per thread (1 row)
+  // FP64 at L <= 512: twiddles as running powers in registers (TwPow),
+  // loaded just before the transform, instead of an 8 KB LDS table
+  constexpr bool TWP = sizeof(C) == 16 && L <= 512;
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
-  __shared__ C tw[L];
+  __shared__ C tw[TWP ? 1 : L];
   __shared__ C sh[SH];
   __shared__ double red[3 * 4];
   __shared__ R sbeta;
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     hr[s] = r[idx];
     hd[s] = d_old[idx];
   }
-  load_twiddles<L>(tw, twg);
+  if constexpr (!TWP) load_twiddles<L>(tw, twg);
 
   // beta of the Polak-Ribiere (PR+) correction, with restart, from the
   // update kernel's partials [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
@@ -226,7 +229,13 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   C val[FftShape<L>::V];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) val[e] = dn[e];
-  fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L, C>(), tw);
+  if constexpr (TWP) {
+    TwPow<L, C> twp;
+    twp.load(twg, t);
+    fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L, C>(), twp);
+  } else {
+    fft_team<L, false, true>(val, t, sh + team * fft_team_lds<L, C>(), tw);
+  }
   if (n < N) {
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
@@ -279,10 +288,12 @@ __global__ __launch_bounds__(256) void k_update(
   // table (11% faster; the FP64 form has no registers to spare, and the
   // direction kernel gained nothing from it)
   constexpr bool TWR = sizeof(C) == 8 && L <= 512;
+  // FP64 at L <= 512: running powers (TwPow), one twiddle per pass
+  constexpr bool TWP = sizeof(C) == 16 && L <= 512;
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;
-  __shared__ C tw[TWR ? 1 : L];
+  __shared__ C tw[(TWR || TWP) ? 1 : L];
   __shared__ C sh[SH];
   __shared__ double red[4 * 4];
   __shared__ R salpha;
@@ -317,7 +328,9 @@ __global__ __launch_bounds__(256) void k_update(
     load_halo2<L>(N, fo, n0, d, hd);
   }
   TwRegs<(TWR ? L : 64), C> twr;
+  TwPow<(TWP ? L : 64), C> twp;
   if constexpr (TWR) twr.load(twg, t);
+  else if constexpr (TWP) twp.load(twg, t);
   else load_twiddles<L>(tw, twg);
 
   // Step length: exact minimiser of the half-quadratic majorant along d
@@ -338,6 +351,7 @@ __global__ __launch_bounds__(256) void k_update(
   // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
   __syncthreads();  // twiddles, step length
   if constexpr (TWR) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twr);
+  else if constexpr (TWP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twp);
   else fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);
   __syncthreads();  // the transform buffers become the x tile
   if constexpr (LATE) {
