@@ -396,7 +396,9 @@ def _gridding_paper_like(c):
 def extra_nufft(c):
     """Section 5's NUFFT precomputation (Kaiser-Bessel, W = 11, grid 2N for
     D = A^H y, 4N for the lag kernel) against the exact FP64-accumulated
-    sums: time per 128-frame batch, relative difference, and one 256^2 frame
+    sums: time per 128-frame batch, relative difference, the whole step with
+    the NUFFT D in complex64 (W = 11) and kept in FP64 (W = 15), each with
+    every frame's distance from the exact-sums result, and one 256^2 frame
     solved with the FP64 iteration from the NUFFT D and spectrum against the
     oracle (exact sums)."""
     torch, recon = c["torch"], c["recon"]
@@ -463,6 +465,39 @@ def extra_nufft(c):
                                 "rel_l2_vs_exact_sums_result_max": float(f"{max(errs):.3e}"),
                                 "rel_l2_all_frames": _rel_summary(_rel_frames(torch, xo,
                                                                               c["x"]))}
+    # the same step with D from a W = 15 NUFFT kept in FP64 (no rounding to
+    # complex64 before the FP64 iteration)
+    W64 = 15
+    gp64 = recon.GridPlan(c["k_host"], N, W=W64)
+    gws64, gwsn64 = gp64.workspace(B)
+    bD64 = torch.empty((B, N, N), dtype=torch.complex128, device="cuda")
+
+    def step64():
+        h = ctypes.c_void_p()
+        recon._check(lib.recon_plan(c["k_host"].ctypes.data, M, N, L, prec, sp.mem.data_ptr(),
+                                    pbytes, st, ctypes.byref(h)))
+        try:
+            recon._check(lib.recon_gram_kernel(h, gws.data_ptr(), gws_n, None, None, st))
+            recon._check(lib.recon_grid_adjoint64(gp64._h, y.data_ptr(), None, B,
+                                                  bD64.data_ptr(), gws64.data_ptr(), gwsn64, st))
+            recon._check(lib.recon_solve_begin_b64(h, bD64.data_ptr(), B, c["lam"], c["delta"],
+                                                   0.0, 1.0, 0, None, ws.data_ptr(), wsn, st))
+            recon._check(lib.recon_solve_iterate(h, c["iters"], ws.data_ptr(), wsn, st))
+            recon._check(lib.recon_solve_end(h, xo.data_ptr(), None, ws.data_ptr(), wsn, st))
+            recon._check(lib.recon_forward(h, xo.data_ptr(), B, yfit.data_ptr(), ws.data_ptr(),
+                                           wsn, st))
+        finally:
+            lib.recon_plan_destroy(h)
+
+    ms64 = cuda_ms(torch, step64, reps=3)
+    ms_d64 = cuda_ms(torch, lambda: gp64.adjoint(y, f64=True), reps=3)
+    out["step_with_nufft_D_fp64"] = {
+        "kernel_width": W64, "beta": round(gp64.beta, 4),
+        "stated_bound": float(f"{4.0 / float(np.i0(gp64.beta)):.2e}"),
+        "D_batch_ms": round(ms_d64, 3),
+        "recons_per_sec": round(B / (ms64 * 1e-3), 2), "ms_per_step": round(ms64, 3),
+        "rel_l2_all_frames": _rel_summary(_rel_frames(torch, xo, c["x"]))}
+    del gws64, bD64
     # control: the exact FP64 sums rounded to complex64 and passed in as D, to
     # separate the iterate's sensitivity to that rounding from the NUFFT's error
     be = exact.adjoint(y)

@@ -236,6 +236,17 @@ recon_status_t recon_solve_begin(recon_plan_t plan, const float* y,
                                  double delta, double lambda0, double alpha0,
                                  int32_t phi, const float* x0, void* ws,
                                  size_t ws_bytes, void* stream);
+/* recon_solve_begin with b given in FP64: b device complex128 [B][N][N],
+ * for plans with RECON_ITER_FP64 (other plans: RECON_E_ARG).  The FP64
+ * iteration amplifies perturbations of b (Section 3.4's D) by up to ~4e5 on
+ * the 256^2 workload, so a b computed in FP64 elsewhere (the NUFFT form of
+ * D, recon_grid_adjoint64) is handed over without rounding it to complex64.
+ * b is read before the call's work completes on `stream` (stream-ordered);
+ * the objective's constant ||y||^2 is taken as 0, as with b_in above. */
+recon_status_t recon_solve_begin_b64(recon_plan_t plan, const double* b, int32_t B,
+                                     double lambda, double delta, double lambda0,
+                                     double alpha0, int32_t phi, const float* x0, void* ws,
+                                     size_t ws_bytes, void* stream);
 recon_status_t recon_solve_iterate(recon_plan_t plan, int32_t iters, void* ws,
                                    size_t ws_bytes, void* stream);
 recon_status_t recon_solve_end(recon_plan_t plan, float* x_out,
@@ -293,8 +304,8 @@ recon_status_t recon_solve_hq_iterate(recon_plan_t plan, int32_t outer, int32_t 
  * With grid oversampling G/N >= 2 and the default beta
  * (pi sqrt(W^2 / s^2 (s - 1/2)^2 - 0.8), s = G/N) the relative error of the
  * sums is bounded by about 4 / I0(beta): 4e-4 (W = 5), 3.5e-6 (W = 7),
- * 3.4e-8 (W = 9), 3.3e-10 (W = 11), 3.1e-12 (W = 13), from the kernel's jump
- * at the edge of its support.
+ * 3.4e-8 (W = 9), 3.3e-10 (W = 11), 3.1e-12 (W = 13), 3.0e-14 (W = 15),
+ * from the kernel's jump at the edge of its support.
  *
  * A grid plan holds, in caller memory (recon_grid_bytes), the trajectory,
  * the per-sample kernel weights and footprints, per-tile sample lists (built
@@ -308,6 +319,8 @@ recon_status_t recon_solve_hq_iterate(recon_plan_t plan, int32_t outer, int32_t 
  *       density weights it is the gridding reconstruction, without them the
  *       NUFFT form of D.  y: device complex64 [B][M]; w: device float64 [M];
  *       out: device complex64 [B][N][N]; ws >= recon_grid_workspace_bytes(B).
+ *   recon_grid_adjoint64: the same sums with out device complex128
+ *       [B][N][N] (no final rounding; for recon_solve_begin_b64).
  *   recon_grid_density: density-compensation weights by the fixed-point
  *       iteration of Pipe and Menon (the paper's [Pipe99]): from w = 1,
  *       `iters` times w <- w / (I S w) with S the spreading of real weights
@@ -330,6 +343,8 @@ void recon_grid_destroy(recon_grid_t grid);
 size_t recon_grid_workspace_bytes(recon_grid_t grid, int32_t B);
 recon_status_t recon_grid_adjoint(recon_grid_t grid, const float* y, const double* w, int32_t B,
                                   float* out, void* ws, size_t ws_bytes, void* stream);
+recon_status_t recon_grid_adjoint64(recon_grid_t grid, const float* y, const double* w, int32_t B,
+                                    double* out, void* ws, size_t ws_bytes, void* stream);
 recon_status_t recon_grid_density(recon_grid_t grid, int32_t iters, double* w, void* ws,
                                   size_t ws_bytes, void* stream);
 size_t recon_gram_nufft_workspace_bytes(int64_t M, int32_t N, int32_t L, int32_t W);

@@ -798,13 +798,16 @@ static recon_status_t check_background(double lambda0, double alpha0) {
   return RECON_OK;
 }
 
-recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
-                                 double lambda, double delta, double lambda0, double alpha0,
-                                 int32_t phi, const float* x0, void* ws, size_t ws_bytes,
-                                 void* stream) {
+// b given in complex64 (b_in) or, for the FP64 iteration, in complex128
+// (b_in64); otherwise b = A^H y.
+static recon_status_t solve_begin(recon_plan_t p, const float* y, const float* b_in,
+                                  const double* b_in64, int32_t B, double lambda, double delta,
+                                  double lambda0, double alpha0, int32_t phi, const float* x0,
+                                  void* ws, size_t ws_bytes, void* stream) {
   g_last_error.clear();
   if (!p) return fail(RECON_E_ARG, "NULL plan");
-  if (!y && !b_in) return fail(RECON_E_ARG, "need y or b");
+  if (!y && !b_in && !b_in64) return fail(RECON_E_ARG, "need y or b");
+  if (b_in64 && !p->f64) return fail(RECON_E_ARG, "an FP64 b needs a plan with RECON_ITER_FP64");
   if (!p->gram_done) return fail(RECON_E_STATE, "recon_gram_kernel has not been called");
   if (phi < 0 || phi > 2) return fail(RECON_E_ARG, "unknown penalty");
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(RECON_E_RANGE, "lambda must be >= 0");
@@ -828,6 +831,10 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
                : adjoint_traced(p, y2, B, w.img(w.lay.b), w.img(w.lay.adj),
                                 reinterpret_cast<float*>(w.base + w.lay.sc), s);
     if (r != RECON_OK) return r;
+  } else if (b_in64) {
+    HIP_TRY(hipMemcpyAsync(w.img64(w.lay.b), b_in64, n_img * sizeof(double2),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_zero_f64((size_t)B, yy, s));
   } else {
     const float2* b2 = reinterpret_cast<const float2*>(b_in);
     if (p->f64)
@@ -875,6 +882,25 @@ recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_
   c.has_y = y != nullptr;
   c.bg = lambda0 > 0.0;
   return RECON_OK;
+}
+
+recon_status_t recon_solve_begin(recon_plan_t p, const float* y, const float* b_in, int32_t B,
+                                 double lambda, double delta, double lambda0, double alpha0,
+                                 int32_t phi, const float* x0, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  return solve_begin(p, y, b_in, nullptr, B, lambda, delta, lambda0, alpha0, phi, x0, ws,
+                     ws_bytes, stream);
+}
+
+recon_status_t recon_solve_begin_b64(recon_plan_t p, const double* b, int32_t B, double lambda,
+                                     double delta, double lambda0, double alpha0, int32_t phi,
+                                     const float* x0, void* ws, size_t ws_bytes, void* stream) {
+  if (!b) {
+    g_last_error.clear();
+    return fail(RECON_E_ARG, "NULL b");
+  }
+  return solve_begin(p, nullptr, nullptr, b, B, lambda, delta, lambda0, alpha0, phi, x0, ws,
+                     ws_bytes, stream);
 }
 
 static recon_status_t get_ctx(recon_plan_t p, void* ws, SolveCtx* out) {
@@ -1416,6 +1442,20 @@ recon_status_t recon_grid_adjoint(recon_grid_t g, const float* y, const double* 
   char* base = static_cast<char*>(ws);
   return grid_type1(g->geom, g->mem, g->lay, reinterpret_cast<const float2*>(y), w,
                     1.0 / g->geom.Nout, B, reinterpret_cast<float2*>(out),
+                    reinterpret_cast<double2*>(base + wl.grid),
+                    reinterpret_cast<double2*>(base + wl.rows), as_stream(stream));
+}
+
+recon_status_t recon_grid_adjoint64(recon_grid_t g, const float* y, const double* w, int32_t B,
+                                    double* out, void* ws, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!g || !y || !out || !ws) return fail(RECON_E_ARG, "NULL argument");
+  if (B < 1) return fail(RECON_E_ARG, "B must be >= 1");
+  const GridWs wl = grid_ws_layout(g->geom, B);
+  if (ws_bytes < wl.total) return fail(RECON_E_NOMEM, "workspace smaller than recon_grid_workspace_bytes");
+  char* base = static_cast<char*>(ws);
+  return grid_type1(g->geom, g->mem, g->lay, reinterpret_cast<const float2*>(y), w,
+                    1.0 / g->geom.Nout, B, reinterpret_cast<double2*>(out),
                     reinterpret_cast<double2*>(base + wl.grid),
                     reinterpret_cast<double2*>(base + wl.rows), as_stream(stream));
 }

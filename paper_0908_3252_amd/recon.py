@@ -62,6 +62,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_gram_apply": (i32, [vp, vp, i32, vp, vp, sz, vp]),
         "recon_solve": (i32, [vp, vp, i32, f64, f64, i32, i32, vp, i32, vp, sz, vp, vp]),
         "recon_solve_begin": (i32, [vp, vp, vp, i32, f64, f64, f64, f64, i32, vp, vp, sz, vp]),
+        "recon_solve_begin_b64": (i32, [vp, vp, i32, f64, f64, f64, f64, i32, vp, vp, sz, vp]),
         "recon_solve_iterate": (i32, [vp, i32, vp, sz, vp]),
         "recon_solve_end": (i32, [vp, vp, vp, vp, sz, vp]),
         "recon_solve_export": (i32, [vp, i32, vp, vp, sz, vp]),
@@ -75,6 +76,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "recon_grid_destroy": (None, [vp]),
         "recon_grid_workspace_bytes": (sz, [vp, i32]),
         "recon_grid_adjoint": (i32, [vp, vp, vp, i32, vp, vp, sz, vp]),
+        "recon_grid_adjoint64": (i32, [vp, vp, vp, i32, vp, vp, sz, vp]),
         "recon_grid_density": (i32, [vp, i32, vp, vp, sz, vp]),
         "recon_gram_nufft_workspace_bytes": (sz, [i64, i32, i32, i32]),
         "recon_gram_kernel_nufft": (i32, [vp, i32, vp, sz, vp, vp, vp]),
@@ -288,13 +290,21 @@ class Plan:
     # resumable form
     def begin(self, y=None, b=None, B=None, lam=0.0, delta=1.0, phi="hyperbolic", x0=None,
               lam0=0.0, alpha0=1.0, hq: bool = False):
-        """hq: bind the half-quadratic workspace (for hq_iterate)."""
+        """hq: bind the half-quadratic workspace (for hq_iterate).  A complex128
+        b (FP64-iteration plans) is handed over without rounding."""
+        import torch
         src = y if y is not None else b
         B = src.shape[0] if B is None else B
         ws, n = self.hq_workspace(B) if hq else self.workspace(B)
-        _check(load().recon_solve_begin(self._h, _ptr(y), _ptr(b), B, float(lam), float(delta),
-                                        float(lam0), float(alpha0), PHI[phi], _ptr(x0),
-                                        ws.data_ptr(), n, _stream()))
+        if y is None and b is not None and b.dtype == torch.complex128:
+            _check(load().recon_solve_begin_b64(self._h, b.contiguous().data_ptr(), B, float(lam),
+                                                float(delta), float(lam0), float(alpha0),
+                                                PHI[phi], _ptr(x0), ws.data_ptr(), n,
+                                                _stream()))
+        else:
+            _check(load().recon_solve_begin(self._h, _ptr(y), _ptr(b), B, float(lam),
+                                            float(delta), float(lam0), float(alpha0), PHI[phi],
+                                            _ptr(x0), ws.data_ptr(), n, _stream()))
         self._active = (B, hq)
 
     def _active_ws(self):
@@ -369,16 +379,18 @@ class GridPlan:
             self._ws[B] = (_dev_buf(n), n)
         return self._ws[B]
 
-    def adjoint(self, y, w=None):
+    def adjoint(self, y, w=None, f64: bool = False):
         """(1/N) sum_l w_l y_l exp(-i 2 pi (kx m + ky n)) for each frame of y
-        (device complex64 [B][M]); w: device float64 [M] or None."""
+        (device complex64 [B][M]); w: device float64 [M] or None.  f64: the
+        result as complex128 (no rounding to complex64)."""
         import torch
         y = y.contiguous()
         B = y.shape[0]
-        out = torch.empty((B, self.N, self.N), dtype=torch.complex64, device="cuda")
+        out = torch.empty((B, self.N, self.N), dtype=torch.complex128 if f64 else torch.complex64,
+                          device="cuda")
         ws, n = self.workspace(B)
-        _check(load().recon_grid_adjoint(self._h, y.data_ptr(), _ptr(w), B, out.data_ptr(),
-                                         ws.data_ptr(), n, _stream()))
+        fn = load().recon_grid_adjoint64 if f64 else load().recon_grid_adjoint
+        _check(fn(self._h, y.data_ptr(), _ptr(w), B, out.data_ptr(), ws.data_ptr(), n, _stream()))
         return out
 
     def density(self, iters: int = 20):

@@ -171,3 +171,79 @@ def test_grid_argument_checks():
     bad[3, 0] = 0.75
     with pytest.raises(recon.ReconError):
         recon.GridPlan(bad, 16)
+
+
+@pytest.mark.parametrize("name,N,spec,W", [CASES[0], CASES[1]])
+def test_nufft_adjoint_fp64_output(name, N, spec, W):
+    """recon_grid_adjoint64: the same sums without the final rounding.  Its
+    complex64 form is exactly the rounding of this result; against the
+    oracle's NUFFT it agrees to FP64 rounding, against the exact sums within
+    the bound."""
+    k = traj(spec, N, N)
+    M = k.shape[0]
+    gp = recon.GridPlan(k, N, W=W)
+    rng = np.random.default_rng(7 + N)
+    y = rand_c(rng, 2, M).astype(np.complex64)
+    b64 = gp.adjoint(dev(y), f64=True)
+    b32 = gp.adjoint(dev(y))
+    torch.cuda.synchronize()
+    assert b64.dtype == torch.complex128
+    np.testing.assert_array_equal(b64.to(torch.complex64).cpu().numpy(), b32.cpu().numpy())
+    b = b64.cpu().numpy()
+    ref = gr.adjoint_nufft(y.astype(np.complex128), k, N, G=gp.G, W=W, beta=gp.beta)
+    exact = oracle.adjoint(y.astype(np.complex128), k, N)
+    e_or, e_ex = rel(b, ref), rel(b, exact)
+    print(f"{name}: FP64 output vs oracle NUFFT {e_or:.2e}, vs exact {e_ex:.2e} "
+          f"(bound {bound(W, gp.G / N):.1e})")
+    assert e_or < 1e-12
+    assert e_ex < bound(W, gp.G / N) + 1e-12
+
+
+def test_fp64_b_into_fp64_iteration():
+    """recon_solve_begin_b64: the oracle's exact b (complex128) handed to the
+    FP64 iteration without rounding gives the oracle's iterate (32^2 workload,
+    200 iterations) to the final complex64 rounding; an FP32-iteration plan
+    refuses an FP64 b."""
+    p = synthetic.make_problem(1)
+    y = p.measured(oracle.forward(p.x_true, p.k)).astype(np.complex64)
+    b = oracle.adjoint(y[0].astype(np.complex128), p.k, p.N)
+    plan = recon.Plan(p.k, p.N, p.L, prec=recon.FP64_ITER64)
+    plan.gram_kernel()
+    plan.begin(b=dev(b[None], np.complex128), lam=p.lam, delta=p.delta)
+    plan.iterate(p.iters)
+    x, st = plan.end()
+    K = oracle.khat(p.k, p.N, p.L)
+    xo = oracle.solve(b, K, p.lam, p.delta, p.iters)
+    e = rel(host(x)[0], xo.astype(np.complex64).astype(np.complex128))
+    print(f"FP64 b, 200 iterations: rel {e:.2e}")
+    assert e < 1e-8
+    assert st["status"][0] == 0
+    p32 = recon.Plan(p.k, p.N, p.L, prec=recon.FP64)
+    p32.gram_kernel()
+    ws, n = p32.workspace(1)
+    st = recon.load().recon_solve_begin_b64(p32._h, dev(b[None], np.complex128).data_ptr(), 1,
+                                            p.lam, p.delta, 0.0, 1.0, 0, None, ws.data_ptr(),
+                                            n, recon._stream())
+    assert st == recon.E_ARG
+
+
+def test_nufft_D_fp64_into_fp64_iteration():
+    """Section 5's NUFFT D at W = 15 (bound 3.0e-14), kept in FP64, as the
+    FP64 iteration's b on the 32^2 workload: the iterate stays at the
+    oracle's exact-sums iterate to the final complex64 rounding."""
+    p = synthetic.make_problem(1)
+    y = p.measured(oracle.forward(p.x_true, p.k)).astype(np.complex64)
+    gp = recon.GridPlan(p.k, p.N, W=15)
+    b64 = gp.adjoint(dev(y), f64=True)
+    b_ex = oracle.adjoint(y[0].astype(np.complex128), p.k, p.N)
+    eb = rel(b64.cpu().numpy()[0], b_ex)
+    plan = recon.Plan(p.k, p.N, p.L, prec=recon.FP64_ITER64)
+    plan.gram_kernel()
+    plan.begin(b=b64, lam=p.lam, delta=p.delta)
+    plan.iterate(p.iters)
+    x, st = plan.end()
+    xo = oracle.solve(b_ex, oracle.khat(p.k, p.N, p.L), p.lam, p.delta, p.iters)
+    e = rel(host(x)[0], xo.astype(np.complex64).astype(np.complex128))
+    print(f"NUFFT D (W = 15) vs exact sums {eb:.2e}; FP64 iteration from it vs oracle {e:.2e}")
+    assert eb < bound(15, gp.G / p.N) + 1e-13
+    assert e < 1e-8

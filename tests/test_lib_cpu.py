@@ -103,3 +103,18 @@ def test_status_strings():
     lib = recon.load()
     for s in range(7):
         assert lib.recon_status_string(s)
+
+
+def test_fp64_b_and_grid_adjoint64_reject_null_arguments_before_any_launch():
+    """recon_solve_begin_b64 and recon_grid_adjoint64 validate their pointers
+    on the host (no plan, no device memory needed)."""
+    lib = recon.load()
+    # NULL plan / NULL b
+    assert lib.recon_solve_begin_b64(None, ctypes.c_void_p(256), 1, 0.01, 0.02, 0.0, 1.0, 0,
+                                     None, ctypes.c_void_p(256), 1 << 20, None) == recon.E_ARG
+    assert lib.recon_solve_begin_b64(ctypes.c_void_p(256), None, 1, 0.01, 0.02, 0.0, 1.0, 0,
+                                     None, ctypes.c_void_p(256), 1 << 20, None) == recon.E_ARG
+    assert b"b" in lib.recon_last_error()
+    # NULL grid plan, output or workspace
+    assert lib.recon_grid_adjoint64(None, ctypes.c_void_p(256), None, 1, ctypes.c_void_p(256),
+                                    ctypes.c_void_p(256), 1 << 20, None) == recon.E_ARG
