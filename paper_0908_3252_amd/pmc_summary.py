@@ -52,6 +52,8 @@ def _kind_of(name: str):
         return "adjoint"
     if "k_forward_" in name:
         return "forward"
+    if "k_colpass_f64_" in name:  # the FP64 column pass at L = 512
+        return "colpass"
     for k in ("k_dir_rowfft", "k_colpass", "k_update"):
         if k + "<" in name or k + "(" in name:
             return k[2:]
