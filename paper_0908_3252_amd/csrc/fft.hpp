@@ -154,23 +154,24 @@ struct IsTwRegs<TwRegs<L, C>> {
   static constexpr bool value = true;
 };
 
-// One twiddle per radix-8 pass in registers (V = 8): W^k of the thread's
-// butterfly; the pass multiplies input r by W^{rk}, formed as the running
-// product W^{(r-1)k} W^k, so that a single product is live at a time.  That
-// needs a third of TwRegs' registers and none of the seven-entry array, at
-// up to six roundings per power instead of two (used in FP64, where that
-// is ~1e-15).
+// One twiddle per radix-8 pass and butterfly in registers: W^k of each of
+// the thread's V/8 butterflies; the pass multiplies input r by W^{rk}, formed
+// as the running product W^{(r-1)k} W^k, so that a single product is live at
+// a time.  At V = 8 that needs a third of TwRegs' registers and none of the
+// seven-entry array, at up to six roundings per power instead of two (used
+// in FP64, where that is ~1e-15).
 template <int L, typename C>
 struct TwPow {
   using S = FftShape<L>;
-  static_assert(S::V == 8, "one butterfly per radix-8 pass");
   static constexpr int NPT = S::NP - 1;
-  C w[NPT > 0 ? NPT : 1];
+  static constexpr int NB8 = S::V / 8;  // butterflies per radix-8 pass
+  C w[NPT > 0 ? NPT : 1][NB8];
   __device__ __forceinline__ void load(const C* __restrict__ g, int t) {
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
       const int ns = S::S0 << (3 * p);  // span of pass p + 1
-      w[p] = g[(t & (ns - 1)) * (L / (8 * ns))];
+#pragma unroll
+      for (int u = 0; u < NB8; ++u) w[p][u] = g[((t + u * S::T) & (ns - 1)) * (L / (8 * ns))];
     }
   }
 };
@@ -212,7 +213,8 @@ __device__ __forceinline__ void fft_pass(C (&v)[FftShape<L>::V], int t, const TW
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = v[u + r * NB];
     if constexpr (NS > 1 && IsTwPow<TW>::value) {
-      C w1 = tw.w[P - 1];
+      static_assert(R == 8, "twiddled passes are radix 8");
+      C w1 = tw.w[P - 1][u];
       if (INV) w1.y = -w1.y;
       C w = w1;
 #pragma unroll

@@ -199,36 +199,46 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   }
 }
 
-// FP64 at L = 512.  A block takes four adjacent columns, one wave-local team
-// (64 threads) per column.  The columns' rows are read and written with
-// lanes along the row segments (4 lanes per 64-byte segment, 64 rows per
-// instruction): read one column per lane, the same bytes took 1.6 x as long
-// (125 against 79 us per 128-frame launch with no transform at all).  Each
-// column goes through LDS to and from its team in the team's own exchange
-// buffer (N <= L/2 values fit in it), the only block barriers being the two
-// around the transforms.  Twiddles as running powers (TwPow) bring it to
-// 124 registers without spills, 4 waves per SIMD (3 with TwRegs: 138-174).
-// The two blocks that share a 128-byte row segment are mapped to one XCD.
-constexpr int COLPASS64_COLS = 4;
+// FP64 at L = 512 and 1024.  A block takes COLS adjacent columns (four at
+// L = 512, two at 1024), one wave-local team (64 threads) per column.  The
+// columns' rows are read and written with lanes along the row segments
+// (COLS lanes per segment, 64 rows per instruction): read one column per
+// lane, the same bytes took 1.6 x as long at L = 512 (125 against 79 us per
+// 128-frame launch with no transform at all).  Each column goes through LDS
+// to and from its team in the team's own exchange buffer (N <= L/2 values
+// fit in it), the only block barriers being the two around the transforms.
+// Twiddles as running powers (TwPow).  L = 512: 124 registers without
+// spills, 4 waves per SIMD (3 with TwRegs: 138-174).  L = 1024 (16 values per
+// thread): ~250 registers, 2 waves per SIMD, the kernel values loaded after
+// the forward transform; 314 -> 233-240 us per 32-frame launch against the
+// earlier 8-column form with a staging tile and an LDS twiddle table.  The
+// blocks that share a 128-byte row segment are mapped to one XCD.
+template <int L>
+struct Col64 {
+  static constexpr int COLS = L == 1024 ? 2 : 4;
+  static constexpr int THREADS = 64 * COLS;
+  static constexpr bool LATEK = L == 1024;  // kernel values after the forward transform
+};
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colpass_f64_512(int N, double2* __restrict__ T,
-                                                         const double* __restrict__ khat_s,
-                                                         double* __restrict__ p3,
-                                                         const double2* __restrict__ twg,
-                                                         const FrameParam* __restrict__ fp,
-                                                         int kit) {
-  constexpr int L = 512;
+template <int L>
+__global__ __launch_bounds__(Col64<L>::THREADS) __attribute__((amdgpu_waves_per_eu(L == 512 ? 4 : 2)))
+void k_colpass_f64(int N, double2* __restrict__ T, const double* __restrict__ khat_s,
+                   double* __restrict__ p3, const double2* __restrict__ twg,
+                   const FrameParam* __restrict__ fp, int kit) {
   using C = double2;
-  constexpr int COLS = COLPASS64_COLS;
-  // team stride: the exchange buffer plus two elements, so that the four
-  // columns of one row (written by four adjacent lanes) fall in different
-  // LDS banks
+  using S = FftShape<L>;
+  constexpr int COLS = Col64<L>::COLS, NT = Col64<L>::THREADS;
+  constexpr int V = S::V;
+  // team stride: the exchange buffer plus two elements, so that the columns
+  // of one row (written by adjacent lanes) fall in different LDS banks
   constexpr int TB = fft_team_lds<L, C>() + 2;
-  static_assert(FftShape<L>::T == 64 && 256 / FftShape<L>::T == COLS, "one team per column");
+  constexpr int RPI = NT / COLS;     // rows per staging instruction (64)
+  constexpr int NS = (L / 2) / RPI;  // staging loads per thread
+  static_assert(S::T == 64 && NT / S::T == COLS, "one wave-local team per column");
   static_assert(TB >= L / 2, "a column fits in its team's buffer");
   if (fp && kit >= fp[blockIdx.y].stop_at) return;
   __shared__ C bufs[COLS * TB];
-  __shared__ double red[4];
+  __shared__ double red[COLS];
   const int f = blockIdx.y;
   int bx = blockIdx.x;
   if (gridDim.x % 8 == 0) bx = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
@@ -236,41 +246,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   C* Tf = T + (size_t)f * N * L;
   const int team = threadIdx.x / 64, t = threadIdx.x % 64;
   const int ci = threadIdx.x % COLS, ri = threadIdx.x / COLS;  // staging: column, first row
-  C ld[4];
+  C ld[NS];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int n = ri + 64 * s;
+  for (int s = 0; s < NS; ++s) {
+    const int n = ri + RPI * s;
     ld[s] = n < N ? Tf[(size_t)n * L + q0 + ci] : cmk<C>(0, 0);
   }
   TwPow<L, C> tw;
   tw.load(twg, t);
   const double* kq = khat_s + (size_t)(q0 + team) * L;
-  double kv[8];
+  double kv[V];
+  if constexpr (!Col64<L>::LATEK) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) kv[e] = kq[t + e * 64];
+    for (int e = 0; e < V; ++e) kv[e] = kq[t + e * 64];
+  }
 #pragma unroll
-  for (int s = 0; s < 4; ++s) bufs[ci * TB + ri + 64 * s] = ld[s];
+  for (int s = 0; s < NS; ++s) bufs[ci * TB + ri + RPI * s] = ld[s];
   __syncthreads();
   C* tb = bufs + team * TB;
-  C val[8];
+  C val[V];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) val[e] = tb[t + 64 * e];
+  for (int e = 0; e < V / 2; ++e) val[e] = tb[t + 64 * e];
   // (the reads above precede the transform's exchange writes within the wave)
   fft_team<L, false, true>(val, t, tb, tw);
+  if constexpr (Col64<L>::LATEK) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) kv[e] = kq[t + e * 64];
+  }
   double acc = 0;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < V; ++e) {
     acc = fma(kv[e], c_abs2(val[e]), acc);
     val[e] = c_scale(val[e], kv[e]);
   }
   fft_team<L, true, false>(val, t, tb, tw);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) tb[t + 64 * e] = val[e];
+  for (int e = 0; e < V / 2; ++e) tb[t + 64 * e] = val[e];
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int n = ri + 64 * s;
-    if (n < N) Tf[(size_t)n * L + q0 + ci] = bufs[ci * TB + ri + 64 * s];
+  for (int s = 0; s < NS; ++s) {
+    const int n = ri + RPI * s;
+    if (n < N) Tf[(size_t)n * L + q0 + ci] = bufs[ci * TB + ri + RPI * s];
   }
   if (p3) {
     double v1[1] = {acc};
@@ -328,7 +344,8 @@ __global__ __launch_bounds__(256) void k_rowifft(int N, const C* __restrict__ T,
   }
 
 int fft_cols_per_block(int L, bool f64) {
-  if (f64 && L == 512) return COLPASS64_COLS;
+  if (f64 && L == 512) return Col64<512>::COLS;
+  if (f64 && L == 1024) return Col64<1024>::COLS;
   switch (L) {
     case 64: return f64 ? ColCfg<64, 2>::COLS : ColCfg<64>::COLS;
     case 128: return f64 ? ColCfg<128, 2>::COLS : ColCfg<128>::COLS;
@@ -354,9 +371,14 @@ static hipError_t colpass_any(int L, int N, int B, C* T, const real_t<C>* khat_s
                               const C* tw, const FrameParam* fp, int k, hipStream_t s) {
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
   if constexpr (sizeof(C) == 16) {
-    if (L == 512) {
+    if (L == 512 || L == 1024) {
       if (N > L / 2) return hipErrorInvalidValue;
-      k_colpass_f64_512<<<dim3(L / COLPASS64_COLS, B), 256, 0, s>>>(N, T, khat_s, p3, tw, fp, k);
+      if (L == 512)
+        k_colpass_f64<512><<<dim3(L / Col64<512>::COLS, B), Col64<512>::THREADS, 0, s>>>(
+            N, T, khat_s, p3, tw, fp, k);
+      else
+        k_colpass_f64<1024><<<dim3(L / Col64<1024>::COLS, B), Col64<1024>::THREADS, 0, s>>>(
+            N, T, khat_s, p3, tw, fp, k);
       return hipGetLastError();
     }
   }
