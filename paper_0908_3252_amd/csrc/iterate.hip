@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   // halo element j of a thread: row j / W, column j % W (W a power of two)
   constexpr int HX = (3 * W + 255) / 256;  // x halo elements per thread (3 rows)
   constexpr int HD = (W + 255) / 256;      // r, d halo elements per thread (1 row)
-  // FP64 at L <= 512: twiddles as running powers in registers (TwPow),
-  // loaded just before the transform, instead of an 8 KB LDS table
-  constexpr bool TWP = sizeof(C) == 16 && L <= 512;
+  // FP64: twiddles as running powers in registers (TwPow),
+  // loaded just before the transform, instead of an 8-16 KB LDS table
+  constexpr bool TWP = sizeof(C) == 16 && L <= 1024;
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
@@ -288,8 +288,8 @@ __global__ __launch_bounds__(256) void k_update(
   // table (11% faster; the FP64 form has no registers to spare, and the
   // direction kernel gained nothing from it)
   constexpr bool TWR = sizeof(C) == 8 && L <= 512;
-  // FP64 at L <= 512: running powers (TwPow), one twiddle per pass
-  constexpr bool TWP = sizeof(C) == 16 && L <= 512;
+  // FP64: running powers (TwPow), one twiddle per pass and butterfly
+  constexpr bool TWP = sizeof(C) == 16 && L <= 1024;
   int bx, f;
   xcd_tile(bx, f);
   if (kit >= fp[f].stop_at) return;
