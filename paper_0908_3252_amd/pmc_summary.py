@@ -52,7 +52,7 @@ def _kind_of(name: str):
         return "adjoint"
     if "k_forward_" in name:
         return "forward"
-    if "k_colpass_f64_" in name:  # the FP64 column pass at L = 512
+    if "k_colpass_f64<" in name:  # the FP64 column pass (L = 512, 1024)
         return "colpass"
     for k in ("k_dir_rowfft", "k_colpass", "k_update"):
         if k + "<" in name or k + "(" in name:
