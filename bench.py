@@ -134,6 +134,28 @@ def cpu_threads():
         return os.cpu_count() or 1
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, cores, numpy / scipy versions and
+    BLAS threads."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    info = {"cpu_model": model, "cpu_count": os.cpu_count(), "numpy": np.__version__,
+            "blas_threads": int(cpu_threads())}
+    try:
+        import scipy
+        info["scipy"] = scipy.__version__
+    except ImportError:  # pragma: no cover
+        pass
+    return info
+
+
 def cpu_baseline_large(torch, recon, prec, sample_iters=40):
     """The FP64 oracle on frame 0 of the large workload: adjoint and Gram
     kernel in full plus a bounded number of iterations, timed on the host;
@@ -522,6 +544,34 @@ def extra_nufft(c):
     return out
 
 
+def extra_paper_shape(c):
+    """The workload the paper times (Section 4.2: 256^2 image, 12 and 24
+    spiral interleaves of 2048 samples, 50 iterations), one frame at a time
+    on the GPU in the benchmark's precision, beside the paper's own timings
+    on its hardware (context only): D took 30 s, 50 iterations 3 min."""
+    torch, recon = c["torch"], c["recon"]
+    N = 256
+    rng = np.random.default_rng([2, 4242])
+    xt = synthetic.ellipse_phantom(N, 40, rng)
+    out = {"paper": {"D_s": 30.0, "iterations_50_s": 180.0,
+                     "hardware": "Athlon 2.1 GHz (C) for D, Matlab for the iterations"}}
+    for inter in (12, 24):
+        k = np.ascontiguousarray(synthetic.spiral_trajectory(N, inter, 2048, 1.0))
+        M = k.shape[0]
+        plan = recon.Plan(k, N, 512, prec=c["prec"])
+        ms_gram = cuda_ms(torch, lambda: plan.gram_kernel(), reps=3)
+        y0 = plan.forward(torch.from_numpy(xt[None].astype(np.complex64)).cuda())
+        noise = torch.from_numpy(synthetic.noise_draws(M, rng)[None].astype(np.complex64)).cuda()
+        y = (y0 + 0.02 * y0.abs().amax() * noise).contiguous()
+        ms_adj = cuda_ms(torch, lambda: plan.adjoint(y), reps=5)
+        ms_solve = cuda_ms(torch, lambda: plan.solve(y, c["lam"], c["delta"], 50,
+                                                      want_stats=False), reps=5)
+        out[f"interleaves_{inter}"] = {"M": M, "gram_kernel_ms": round(ms_gram, 3),
+                                       "D_ms": round(ms_adj, 3),
+                                       "solve_50_ms_incl_D": round(ms_solve, 3)}
+    return out
+
+
 def extra_served_mixed(args, c):
     """The mixed-size served stream (N in {64..384}, 8/16/32 interleaves,
     Poisson arrivals) at the given rates, FP64 iteration and the precision
@@ -877,16 +927,19 @@ def main():
         log("cpu baseline (FP64 oracle, one frame)")
         cb, rel, oracle_frame = cpu_baseline(args, torch, recon, prec)
         out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
+        out["cpu_baseline"]["host"] = host_info()
         if rel is not None:
             out["rel_l2_vs_oracle_one_frame"] = rel
     if not args.no_extras and args.workload == "series256" and args.criterion == "plain":
         ctx = dict(torch=torch, recon=recon, lib=lib, prob=prob, y=y, x=x, B=B, N=N, L=L, M=M,
+                   prec=prec,
                    iters=iters, k_host=k_host, lam=c_lam, delta=c_delta, stream=stream,
                    oracle_frame=oracle_frame)
         for name, fn in (("precision_form", extra_precision_form),
                          ("half_quadratic_vs_cg", extra_half_quadratic),
                          ("gridding_comparison", extra_gridding),
-                         ("nufft_precompute", extra_nufft)):
+                         ("nufft_precompute", extra_nufft),
+                         ("paper_shape", extra_paper_shape)):
             log(f"extra: {name}")
             out[name] = fn(ctx)
         if args.mixed_count > 0:
