@@ -919,7 +919,18 @@ static recon_status_t get_ctx(recon_plan_t p, void* ws, SolveCtx* out) {
 template <typename C, typename K>
 static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0,
                                        int iters, const C* tw, const K* khat, hipStream_t s) {
-  const int N = p->N, L = p->L, B = c.B;
+  const int N = p->N, L = p->L;
+  // A slot pool launches over slots 0 .. (highest slot still running) only:
+  // the slots above it are idle for the whole call, and their blocks would
+  // only start and exit.  (The scheduler fills the lowest free slot first.)
+  int B = c.B;
+  if (c.pool) {
+    int hi = 0;
+    for (int sl = 0; sl < c.B; ++sl)
+      if (c.stop_at[sl] > k0) hi = sl + 1;
+    if (hi == 0) return RECON_OK;  // nothing running
+    B = hi;
+  }
   C* T = w.at<C>(w.lay.T);
   C* r = w.at<C>(w.lay.r);
   for (int it = 0; it < iters; ++it) {
