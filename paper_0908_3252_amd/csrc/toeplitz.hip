@@ -62,14 +62,13 @@ __global__ __launch_bounds__(256) void k_rowfft_plain(int N, const C* __restrict
 // is its share of Re<v, Q v>.  FP64 elements (ES = 2) halve the columns per
 // block (and the threads at L = 512) so that the tile stays within LDS.
 template <int L, int ES = 1>
+// (FP64 at L = 512 and 1024 has its own kernel, k_colpass_f64 below.)
 struct ColCfg {
+  static_assert(ES == 1 || L <= 256, "FP64 at L >= 512 uses k_colpass_f64");
   static constexpr int T = FftShape<L>::T;
-  static constexpr int THREADS = ((L == 512 && ES == 1) || (L == 1024 && ES == 2)) ? 512 : 256;
+  static constexpr int THREADS = (L == 512 && ES == 1) ? 512 : 256;
   static constexpr int TEAMS = THREADS / T;
-  // (FP64 at L >= 1024 keeps 8 columns: 128-byte row segments, whole cache
-  // lines; that form is register-bound to one block per CU anyway)
-  static constexpr int COLS = (L >= 1024 && ES == 2) ? 8
-                              : ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
+  static constexpr int COLS = ((L <= 64) ? 32 : (L <= 512 ? 16 : 8)) / ES;
   static_assert(COLS % TEAMS == 0 || TEAMS > COLS, "columns per block vs teams");
 };
 
@@ -350,8 +349,8 @@ int fft_cols_per_block(int L, bool f64) {
     case 64: return f64 ? ColCfg<64, 2>::COLS : ColCfg<64>::COLS;
     case 128: return f64 ? ColCfg<128, 2>::COLS : ColCfg<128>::COLS;
     case 256: return f64 ? ColCfg<256, 2>::COLS : ColCfg<256>::COLS;
-    case 512: return f64 ? ColCfg<512, 2>::COLS : ColCfg<512>::COLS;
-    case 1024: return f64 ? ColCfg<1024, 2>::COLS : ColCfg<1024>::COLS;
+    case 512: return ColCfg<512>::COLS;
+    case 1024: return ColCfg<1024>::COLS;
     case 2048: return ColCfg<2048>::COLS;
     default: return 1;
   }
@@ -364,6 +363,16 @@ static hipError_t rowfft_plain_any(int L, int N, int B, const C* v, C* T, const 
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
   RECON_L_SWITCH(L, (k_rowfft_plain<LL, C><<<grid, 256, 0, s>>>(N, v, T, tw)));
   return hipGetLastError();
+}
+
+// The generic column kernel (FP64 at L >= 512 goes to k_colpass_f64 and is
+// not built here).
+template <int LL, typename C>
+static void colpass_generic(dim3 grid, int N, C* T, const real_t<C>* khat_s, double* p3,
+                            const C* tw, const FrameParam* fp, int k, hipStream_t s) {
+  if constexpr (sizeof(C) == 8 || LL <= 256)
+    k_colpass<LL, C><<<grid, ColCfg<LL, sizeof(C) / 8>::THREADS, 0, s>>>(N, T, khat_s, p3, tw,
+                                                                          fp, k);
 }
 
 template <typename C>
@@ -383,8 +392,7 @@ static hipError_t colpass_any(int L, int N, int B, C* T, const real_t<C>* khat_s
     }
   }
   dim3 grid(L / fft_cols_per_block(L, sizeof(C) == 16), B);
-  RECON_L_SWITCH(L, (k_colpass<LL, C><<<grid, ColCfg<LL, sizeof(C) / 8>::THREADS, 0, s>>>(
-                        N, T, khat_s, p3, tw, fp, k)));
+  RECON_L_SWITCH(L, (colpass_generic<LL, C>(grid, N, T, khat_s, p3, tw, fp, k, s)));
   return hipGetLastError();
 }
 
