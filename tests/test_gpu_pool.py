@@ -123,6 +123,34 @@ def test_pool_plain_workload_shape_bitwise():
         assert bitwise(xg, xr), f"frame {f}"
 
 
+@pytest.mark.parametrize("prec", [recon.FP64, recon.FP64_ITER64])
+def test_pool_launch_range_follows_running_slots(prec):
+    """A pool step launches over the slots up to the highest running one: a
+    step with only slot 1 running (slots 2..5 idle), then slot 5 admitted
+    while slot 1 still runs, then slot 1 finishing first.  Both results equal
+    their standalone solves bit for bit."""
+    p = synthetic.make_frames(3, frames=2, N=48, S=192, I=8, K=10)
+    plan = recon.Plan(p.k, p.N, prec=prec)
+    plan.gram_kernel()
+    y0 = plan.forward(torch.from_numpy(p.x_true.astype(np.complex64)).cuda())
+    nz = torch.from_numpy(p.noise.astype(np.complex64)).cuda()
+    y = (y0 + p.noise_c * y0.abs().amax(dim=1, keepdim=True) * nz).contiguous()
+    pool = recon.Pool(plan, 6)
+    pool.admit(1, y[0], p.lam, p.delta, 20)   # k = 0, stops at 20
+    pool.step(8)                              # launches cover slots 0..1
+    pool.admit(5, y[1], p.lam, p.delta, 15)   # k = 8, stops at 23
+    pool.step(12)                             # k = 20: slot 1 done
+    x0 = torch.empty((p.N, p.N), dtype=torch.complex64, device="cuda")
+    pool.retire(1, x0)
+    pool.step(3)                              # k = 23: slots 0..5, slot 5 only
+    x1 = torch.empty((p.N, p.N), dtype=torch.complex64, device="cuda")
+    pool.retire(5, x1)
+    pool.step(4)                              # nothing running: no launch
+    for f, xg, it in ((0, x0, 20), (1, x1, 15)):
+        xr, _ = standalone(plan, y[f], p.lam, p.delta, it)
+        assert bitwise(xg, xr), f"frame {f}"
+
+
 def test_pool_state_errors():
     N, L = 32, 64
     k, xs = frames_for(N, 4, 256, 1.0, 2, seed=5)
