@@ -270,7 +270,7 @@ recon_status_t recon_solve_export(recon_plan_t plan, int32_t field, float* out,
  * which lies above J and touches it at xbar, so J decreases at every outer
  * iteration.  Each inner step applies Q once.
  *   recon_hq_workspace_bytes: workspace of the half-quadratic solver (the
- *                      recon_workspace_bytes layout plus two images); 0 on
+ *                      recon_workspace_bytes layout plus one image); 0 on
  *                      invalid sizes or precision.
  *   recon_solve_hq:    as recon_solve (x0 = 0 or the contents of x), with
  *                      outer x inner steps; stats.grad_ratio is the true

@@ -110,7 +110,7 @@ PlanLayout plan_layout(int64_t M, int32_t N, int32_t L, int32_t prec_full) {
 }
 
 struct WsLayout {
-  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, yyp, sc, adj, xb, g, total;
+  size_t b, x[2], r, d[2], qd, T, p1, p3, p4, pg0, pobj, params, yy, yyp, sc, adj, xb, total;
   int rows, nb1, nb3, nb4, adj_splits;
 };
 
@@ -160,11 +160,8 @@ WsLayout ws_layout(int64_t M, int32_t N, int32_t L, int32_t B, bool f64, bool hq
     const size_t a64 = part_frames(adjoint64_splits(M, N), adjoint64_group(M, N));
     w.adj = take((a32 > a64 ? a32 : a64) * N * N * sizeof(double2));
   }
-  w.xb = w.g = 0;
-  if (hq) {
-    w.xb = take(img);
-    w.g = take(img);
-  }
+  w.xb = 0;
+  if (hq) w.xb = take(img);
   w.total = off;
   return w;
 }
@@ -961,8 +958,9 @@ static recon_status_t run_iterations_t(recon_plan_t p, const SolveCtx& c, const 
 // Half-quadratic minimisation: `outer` times, freeze the penalty weights at
 // the current image and run `inner` linear-CG steps on the surrogate; then
 // the true gradient's norm into the update partials (for the statistics).
-// The step counter k advances by one per inner step (x, d buffers as in
-// run_iterations).
+// An inner step is the conjugate-gradient step's three kernels with the
+// weights taken from the frozen image xb.  The step counter k advances by
+// one per inner step (x, d buffers as in run_iterations).
 template <typename C, typename K>
 static recon_status_t run_hq_t(recon_plan_t p, const SolveCtx& c, const Ws& w, int k0, int outer,
                                int inner, const C* tw, const K* khat, hipStream_t s) {
@@ -970,8 +968,6 @@ static recon_status_t run_hq_t(recon_plan_t p, const SolveCtx& c, const Ws& w, i
   C* T = w.at<C>(w.lay.T);
   C* r = w.at<C>(w.lay.r);
   C* xb = w.at<C>(w.lay.xb);
-  C* g = w.at<C>(w.lay.g);
-  C* qd = w.at<C>(w.lay.qd);
   int k = k0;
   for (int o = 0; o < outer; ++o) {
     HIP_TRY(launch_hq_freeze(N, B, w.lay.nb4, w.at<C>(w.lay.x[k & 1]), xb, w.dbl(w.lay.p4), s));
@@ -982,20 +978,18 @@ static recon_status_t run_hq_t(recon_plan_t p, const SolveCtx& c, const Ws& w, i
       C* x_new = w.at<C>(w.lay.x[(k + 1) & 1]);
       {
         TraceScope ts(TK_DIR, s);
-        HIP_TRY(launch_hq_dir(c.phi, N, R, B, r, d_old, d_new, g, x_old, xb, w.dbl(w.lay.p4),
-                              w.lay.nb4, w.dbl(w.lay.p1), w.params(), c.bg, s));
+        HIP_TRY(launch_dir_rowfft(L, c.phi, N, B, r, d_old, d_new, x_old, T, w.dbl(w.lay.p4),
+                                  w.lay.nb4, w.dbl(w.lay.p1), w.params(), tw, k, c.bg, s, xb));
       }
-      HIP_TRY(launch_rowfft_plain(L, N, B, d_new, T, tw, s));
       {
         TraceScope ts(TK_COL, s);
         HIP_TRY(launch_colpass(L, N, B, T, khat, w.dbl(w.lay.p3), tw, w.params(), k, s));
       }
-      HIP_TRY(launch_rowifft(L, N, B, T, qd, tw, w.params(), k, s));
       {
         TraceScope ts(TK_UPDATE, s);
-        HIP_TRY(launch_hq_update(c.phi, N, R, B, x_old, x_new, d_new, r, qd, g, xb,
-                                 w.dbl(w.lay.p1), w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3,
-                                 w.dbl(w.lay.p4), w.params(), c.bg, s));
+        HIP_TRY(launch_update(L, c.phi, N, B, T, x_old, x_new, d_new, r, w.dbl(w.lay.p1),
+                              w.lay.nb1, w.dbl(w.lay.p3), w.lay.nb3, w.dbl(w.lay.p4), w.params(),
+                              tw, k, c.bg, s, xb));
       }
     }
   }

@@ -51,12 +51,15 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& f) {
 }
 
 // ------------------------------------------------------- direction + rows
-template <int L, int PHI, typename C, bool BG>
+// HQ: one inner step of the half-quadratic minimiser instead (the weights
+// and the background weight frozen at the image xb; gradient and curvature of
+// the quadratic surrogate): an extra tile of xb rows beside the x tile.
+template <int L, int PHI, typename C, bool BG, bool HQ>
 __global__ __launch_bounds__(256) void k_dir_rowfft(
     int N, const C* __restrict__ r, const C* __restrict__ d_old, C* __restrict__ d_new,
     const C* __restrict__ x, C* __restrict__ T, const double* __restrict__ p4, int nb4,
     double* __restrict__ p1, const FrameParam* __restrict__ fp, const C* __restrict__ twg,
-    int kit) {
+    int kit, const C* __restrict__ xb) {
   using RC = RowCfg<L>;
   using R = real_t<C>;
   constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
@@ -76,10 +79,15 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   if (kit >= fp[f].stop_at) return;  // frame idle in this iteration (block-uniform)
   __shared__ C tw[TWP ? 1 : L];
   __shared__ C sh[SH];
+  // HQ: xb rows n0-1 .. n0+ROWS (the last x row's partner comes from memory);
+  // ROWS + 2 rows keep the FP64 kernel at L = 512 within three blocks per CU
+  constexpr int BT = (ROWS + 2) * W;
+  __shared__ C sbt[HQ ? BT : 1];
   __shared__ double red[3 * 4];
   __shared__ R sbeta;
   C* Xt = sh;  // tile row i <-> image row n0 - 1 + i (stride N)
   C* Dt = sh;  // after the gradients: tile row i <-> image row n0 + i
+  C* Bt = sbt;  // HQ: xb, rows as the x tile
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -145,6 +153,21 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS + sel - 1;
     if (j < 3 * W && m < N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
   }
+  if constexpr (HQ) {  // xb straight into its tile (no register copies)
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int m = t + e * TT;
+      if (n < N && m < N) Bt[(team + 1) * N + m] = xb[fo + (size_t)n * N + m];
+    }
+#pragma unroll
+    for (int s = 0; s < RC::HX2; ++s) {
+      const int j = threadIdx.x + s * 256;
+      const int sel = j / W, m = j % W;  // sel 0: n0-1, 1: n0+ROWS
+      const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+      if (j < 2 * W && m < N && img >= 0 && img < N)
+        Bt[(img - n0 + 1) * N + m] = xb[fo + (size_t)img * N + m];
+    }
+  }
   __syncthreads();
   const R bf = sbeta;
 
@@ -159,15 +182,28 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     wdn[e] = wrt[e] = 0;
     if (n < N && m < N) {
       const C* mid = Xt + (team + 1) * N;
-      const C div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
-                                       n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
-                                       wrt[e]);
-      const C g = grad_full<BG>(ro[e], div, xo[e], lam, lam0, alpha0);
+      C g;
+      C wx = xo[e];  // the image the background weight is taken at
+      if constexpr (HQ) {
+        const C* bmid = Bt + (team + 1) * N;
+        const C div = divergence_frozen_fw<PHI>(
+            n > 0 ? mid - N : nullptr, mid, n + 1 < N ? mid + N : nullptr,
+            n > 0 ? bmid - N : nullptr, bmid, n + 1 < N ? bmid + N : nullptr, m, N, delta,
+            wdn[e], wrt[e]);
+        wx = bmid[m];
+        g = grad_frozen<BG>(ro[e], div, xo[e], wx, lam, lam0, alpha0);
+      } else {
+        const C div = divergence_fw<PHI>(n > 0 ? mid - N : nullptr, mid,
+                                         n + 1 < N ? mid + N : nullptr, m, N, delta, wdn[e],
+                                         wrt[e]);
+        g = grad_full<BG>(ro[e], div, xo[e], lam, lam0, alpha0);
+      }
       dn[e] = cmk<C>(rfma(bf, dv[e].x, -g.x), rfma(bf, dv[e].y, -g.y));
       d_new[fo + (size_t)n * N + m] = dn[e];
       gd += (double)g.x * (double)dn[e].x + (double)g.y * (double)dn[e].y;
-      // background curvature w0(|x|) |d|^2 (majorant of Omega_0 along d)
-      if constexpr (BG) cv0 += (double)bg_weight(xo[e], lam0, alpha0) * (double)c_abs2(dn[e]);
+      // background curvature w0(|x|) |d|^2 (majorant of Omega_0 along d;
+      // HQ: the frozen w0(|xb|))
+      if constexpr (BG) cv0 += (double)bg_weight(wx, lam0, alpha0) * (double)c_abs2(dn[e]);
     }
   }
   if (n0 + ROWS < N) {
@@ -177,8 +213,18 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       const int m = threadIdx.x + s * 256;
       if (m < N) {
         const C* mid = Xt + (ROWS + 1) * N;
-        const C div = divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
-        const C g = grad_full<BG>(hr[s], div, mid[m], lam, lam0, alpha0);
+        C g;
+        if constexpr (HQ) {
+          const C* bmid = Bt + (ROWS + 1) * N;
+          const C div = divergence_frozen<PHI>(
+              mid - N, mid, nh + 1 < N ? mid + N : nullptr, bmid - N, bmid,
+              nh + 1 < N ? xb + fo + (size_t)(nh + 1) * N : nullptr, m, N, delta);
+          g = grad_frozen<BG>(hr[s], div, mid[m], bmid[m], lam, lam0, alpha0);
+        } else {
+          const C div =
+              divergence<PHI>(mid - N, mid, nh + 1 < N ? mid + N : nullptr, m, N, delta);
+          g = grad_full<BG>(hr[s], div, mid[m], lam, lam0, alpha0);
+        }
         dh[s] = cmk<C>(rfma(bf, hd[s].x, -g.x), rfma(bf, hd[s].y, -g.y));
       }
     }
@@ -269,12 +315,15 @@ __device__ __forceinline__ void load_halo2(int N, size_t fo, int n0, const C* __
   }
 }
 
-template <int L, int PHI, typename C, bool BG>
+// HQ: the update of an inner half-quadratic step (weights frozen at xb; an
+// extra tile of xb rows).
+template <int L, int PHI, typename C, bool BG, bool HQ>
 __global__ __launch_bounds__(256) void k_update(
     int N, const C* __restrict__ T, const C* __restrict__ x_old, C* __restrict__ x_new,
     const C* __restrict__ d, C* __restrict__ r, const double* __restrict__ p1, int nb1,
     const double* __restrict__ p3, int nb3, double* __restrict__ p4,
-    const FrameParam* __restrict__ fp, const C* __restrict__ twg, int kit) {
+    const FrameParam* __restrict__ fp, const C* __restrict__ twg, int kit,
+    const C* __restrict__ xb) {
   using RC = RowCfg<L>;
   using R = real_t<C>;
   constexpr int TT = RC::TT, ROWS = RC::ROWS, W = RC::W, EPT = RC::EPT;
@@ -295,10 +344,12 @@ __global__ __launch_bounds__(256) void k_update(
   if (kit >= fp[f].stop_at) return;
   __shared__ C tw[(TWR || TWP) ? 1 : L];
   __shared__ C sh[SH];
+  __shared__ C sbt[HQ ? XT : 1];
   __shared__ double red[4 * 4];
   __shared__ R salpha;
   C* Xt = sh;                      // x, then x + alpha d (in place); row i <-> image row n0-1+i
   C* fb = sh;                      // exchange buffers of the row transforms
+  C* Bt = sbt;                     // HQ: xb, rows as the x tile
   const int n0 = bx * ROWS;
   const size_t fo = (size_t)f * N * N;
   const int team = threadIdx.x / TT, t = threadIdx.x % TT;
@@ -372,6 +423,21 @@ __global__ __launch_bounds__(256) void k_update(
     const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
     if (j < 2 * W && m < N && img >= 0 && img < N) Xt[(img - n0 + 1) * N + m] = hx[s];
   }
+  if constexpr (HQ) {  // the xb tile, same rows, straight from memory
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int m = t + e * TT;
+      if (n < N && m < N) Bt[(team + 1) * N + m] = xb[fo + (size_t)n * N + m];
+    }
+#pragma unroll
+    for (int s = 0; s < HX; ++s) {
+      const int j = threadIdx.x + s * 256;
+      const int sel = j / W, m = j % W;
+      const int img = sel == 0 ? n0 - 1 : n0 + ROWS;
+      if (j < 2 * W && m < N && img >= 0 && img < N)
+        Bt[(img - n0 + 1) * N + m] = xb[fo + (size_t)img * N + m];
+    }
+  }
   __syncthreads();  // x tile, twiddles, step length
   const R af = salpha;
   // go: the old gradient (LATE: the old divergence; the gradient is formed
@@ -383,10 +449,19 @@ __global__ __launch_bounds__(256) void k_update(
     go[e] = cmk<C>(0, 0);
     if (n < N && m < N) {
       const C* mo = Xt + (team + 1) * N;
-      const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
-                                      n + 1 < N ? mo + N : nullptr, m, N, delta);
-      if constexpr (LATE) go[e] = div_o;
-      else go[e] = grad_full<BG>(ro[e], div_o, xo[e], lam, lam0, alpha0);
+      if constexpr (HQ) {
+        const C* bm = Bt + (team + 1) * N;
+        const C div_o = divergence_frozen<PHI>(
+            n > 0 ? mo - N : nullptr, mo, n + 1 < N ? mo + N : nullptr,
+            n > 0 ? bm - N : nullptr, bm, n + 1 < N ? bm + N : nullptr, m, N, delta);
+        if constexpr (LATE) go[e] = div_o;
+        else go[e] = grad_frozen<BG>(ro[e], div_o, xo[e], bm[m], lam, lam0, alpha0);
+      } else {
+        const C div_o = divergence<PHI>(n > 0 ? mo - N : nullptr, mo,
+                                        n + 1 < N ? mo + N : nullptr, m, N, delta);
+        if constexpr (LATE) go[e] = div_o;
+        else go[e] = grad_full<BG>(ro[e], div_o, xo[e], lam, lam0, alpha0);
+      }
     }
   }
   __syncthreads();  // every read of the old x is done
@@ -429,11 +504,21 @@ __global__ __launch_bounds__(256) void k_update(
     if (n < N && m < N) {
       const size_t idx = fo + (size_t)n * N + m;
       const C* mn = Xt + (team + 1) * N;
-      const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
-                                      n + 1 < N ? mn + N : nullptr, m, N, delta);
-      const C goe = LATE ? grad_full<BG>(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
       const C rn = c_axpy(af, val[e], ro[e]);
-      const C gn = grad_full<BG>(rn, div_n, mn[m], lam, lam0, alpha0);
+      C goe, gn;
+      if constexpr (HQ) {
+        const C* bm = Bt + (team + 1) * N;
+        const C div_n = divergence_frozen<PHI>(
+            n > 0 ? mn - N : nullptr, mn, n + 1 < N ? mn + N : nullptr,
+            n > 0 ? bm - N : nullptr, bm, n + 1 < N ? bm + N : nullptr, m, N, delta);
+        goe = LATE ? grad_frozen<BG>(ro[e], go[e], xo[e], bm[m], lam, lam0, alpha0) : go[e];
+        gn = grad_frozen<BG>(rn, div_n, mn[m], bm[m], lam, lam0, alpha0);
+      } else {
+        const C div_n = divergence<PHI>(n > 0 ? mn - N : nullptr, mn,
+                                        n + 1 < N ? mn + N : nullptr, m, N, delta);
+        goe = LATE ? grad_full<BG>(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
+        gn = grad_full<BG>(rn, div_n, mn[m], lam, lam0, alpha0);
+      }
       x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
@@ -476,37 +561,45 @@ __global__ __launch_bounds__(256) void k_update(
     default: return hipErrorInvalidValue;             \
   }
 
-template <typename C, bool BG>
+template <typename C, bool BG, bool HQ>
 static hipError_t dir_rowfft_t(int L, int phi, int N, int B, const C* r, const C* d_old,
                                C* d_new, const C* x, C* T, const double* p4, int nb4, double* p1,
-                               const FrameParam* fp, const C* tw, int k, hipStream_t s) {
+                               const FrameParam* fp, const C* tw, int k, const C* xb,
+                               hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP, C, BG><<<grid, 256, 0, s>>>(
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_dir_rowfft<LL, PP, C, BG, HQ><<<grid, 256, 0, s>>>(
                                                         N, r, d_old, d_new, x, T, p4, nb4, p1,
-                                                        fp, tw, k))));
+                                                        fp, tw, k, xb))));
   return hipGetLastError();
 }
 
 template <typename C>
 static hipError_t dir_rowfft_any(int L, int phi, int N, int B, const C* r, const C* d_old,
                                  C* d_new, const C* x, C* T, const double* p4, int nb4, double* p1,
-                                 const FrameParam* fp, const C* tw, int k, bool bg,
+                                 const FrameParam* fp, const C* tw, int k, bool bg, const C* xb,
                                  hipStream_t s) {
   if (N > L / 2) return hipErrorInvalidValue;
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
-  return bg ? dir_rowfft_t<C, true>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, s)
-            : dir_rowfft_t<C, false>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k,
-                                     s);
+  if (xb)
+    return bg ? dir_rowfft_t<C, true, true>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp,
+                                            tw, k, xb, s)
+              : dir_rowfft_t<C, false, true>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp,
+                                             tw, k, xb, s);
+  return bg ? dir_rowfft_t<C, true, false>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp,
+                                           tw, k, xb, s)
+            : dir_rowfft_t<C, false, false>(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp,
+                                            tw, k, xb, s);
 }
 
-template <typename C, bool BG>
+template <typename C, bool BG, bool HQ>
 static hipError_t update_t(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
                            const C* d, C* r, const double* p1, int nb1, const double* p3, int nb3,
-                           double* p4, const FrameParam* fp, const C* tw, int k, hipStream_t s) {
+                           double* p4, const FrameParam* fp, const C* tw, int k, const C* xb,
+                           hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C, BG><<<grid, 256, 0, s>>>(
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C, BG, HQ><<<grid, 256, 0, s>>>(
                                                         N, T, x_old, x_new, d, r, p1, nb1, p3,
-                                                        nb3, p4, fp, tw, k))));
+                                                        nb3, p4, fp, tw, k, xb))));
   return hipGetLastError();
 }
 
@@ -514,39 +607,47 @@ template <typename C>
 static hipError_t update_any(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
                              const C* d, C* r, const double* p1, int nb1, const double* p3,
                              int nb3, double* p4, const FrameParam* fp, const C* tw, int k,
-                             bool bg, hipStream_t s) {
+                             bool bg, const C* xb, hipStream_t s) {
   if (N > L / 2) return hipErrorInvalidValue;
   if (sizeof(C) == 16 && L > 1024) return hipErrorInvalidValue;
-  return bg ? update_t<C, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw,
-                                k, s)
-            : update_t<C, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp,
-                                 tw, k, s);
+  if (xb)
+    return bg ? update_t<C, true, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4,
+                                        fp, tw, k, xb, s)
+              : update_t<C, false, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3,
+                                         p4, fp, tw, k, xb, s);
+  return bg ? update_t<C, true, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4,
+                                       fp, tw, k, xb, s)
+            : update_t<C, false, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4,
+                                        fp, tw, k, xb, s);
 }
 
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, int k, bool bg, hipStream_t s) {
-  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, s);
+                             const float2* tw, int k, bool bg, hipStream_t s, const float2* xb) {
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, xb, s);
 }
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
                              const double2* d_old, double2* d_new, const double2* x, double2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const double2* tw, int k, bool bg, hipStream_t s) {
-  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, s);
+                             const double2* tw, int k, bool bg, hipStream_t s,
+                             const double2* xb) {
+  return dir_rowfft_any(L, phi, N, B, r, d_old, d_new, x, T, p4, nb4, p1, fp, tw, k, bg, xb, s);
 }
 
 hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const float2* tw, int k, bool bg, hipStream_t s) {
-  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, s);
+                         const float2* tw, int k, bool bg, hipStream_t s, const float2* xb) {
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, xb,
+                    s);
 }
 hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
                          double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const double2* tw, int k, bool bg, hipStream_t s) {
-  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, s);
+                         const double2* tw, int k, bool bg, hipStream_t s, const double2* xb) {
+  return update_any(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4, fp, tw, k, bg, xb,
+                    s);
 }
 
 }  // namespace recon

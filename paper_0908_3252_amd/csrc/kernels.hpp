@@ -63,27 +63,34 @@ hipError_t launch_rowifft(int L, int N, int B, const double2* T, double2* out,
 // Direction: g = 2 r + grad R(x) (recomputed), d_new = -g + beta d_old (beta
 // from the update partials, PR+ with restart), partials Re<g, d_new> and
 // sum w(x)|D d_new|^2, and the row pass of the Gram apply on d_new.
+// xb non-null: the inner step of the half-quadratic minimiser, every penalty
+// weight (edges and background) frozen at the image xb.
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const float2* r,
                              const float2* d_old, float2* d_new, const float2* x, float2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const float2* tw, int k, bool bg, hipStream_t s);
+                             const float2* tw, int k, bool bg, hipStream_t s,
+                             const float2* xb = nullptr);
 hipError_t launch_dir_rowfft(int L, int phi, int N, int B, const double2* r,
                              const double2* d_old, double2* d_new, const double2* x, double2* T,
                              const double* p4, int nb4, double* p1, const FrameParam* fp,
-                             const double2* tw, int k, bool bg, hipStream_t s);
+                             const double2* tw, int k, bool bg, hipStream_t s,
+                             const double2* xb = nullptr);
 // Row inverse pass of the Gram apply fused with the update: Qd = rows of
 // IFFT(T) cropped; alpha from the partials; x_new = x + alpha d,
 // r += alpha Qd; partials for beta from g_old (recomputed from r, x) and
 // g_new = 2 r + grad R(x_new).  bg: some frame of the launch has the
 // background penalty on (lam0 > 0); without it the term is compiled out.
+// xb non-null: the half-quadratic inner step (weights frozen at xb).
 hipError_t launch_update(int L, int phi, int N, int B, const float2* T, const float2* x_old,
                          float2* x_new, const float2* d, float2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const float2* tw, int k, bool bg, hipStream_t s);
+                         const float2* tw, int k, bool bg, hipStream_t s,
+                         const float2* xb = nullptr);
 hipError_t launch_update(int L, int phi, int N, int B, const double2* T, const double2* x_old,
                          double2* x_new, const double2* d, double2* r, const double* p1, int nb1,
                          const double* p3, int nb3, double* p4, const FrameParam* fp,
-                         const double2* tw, int k, bool bg, hipStream_t s);
+                         const double2* tw, int k, bool bg, hipStream_t s,
+                         const double2* xb = nullptr);
 // Initial state: x = x0 (or 0), r = Qx0 - b (Qx0 NULL: -b), d = 0; partials
 // such that the first direction is -g, g = 2r + grad R(x0).  R rows per block.
 hipError_t launch_init(int phi, int N, int R, int B, const float2* b,
@@ -126,27 +133,8 @@ hipError_t launch_hq_freeze(int N, int B, int nb4, const float2* x, float2* xb, 
                             hipStream_t s);
 hipError_t launch_hq_freeze(int N, int B, int nb4, const double2* x, double2* xb, double* p4,
                             hipStream_t s);
-// Surrogate gradient g (stored), direction d_new (PR+ from p4), step partials
-// p1 [Re<g,d>, sum w(D xb)|D d|^2, sum w0(xb)|d|^2]; R rows per block.
-hipError_t launch_hq_dir(int phi, int N, int R, int B, const float2* r, const float2* d_old,
-                         float2* d_new, float2* g, const float2* x, const float2* xb,
-                         const double* p4, int nb4, double* p1, const FrameParam* fp, bool bg,
-                         hipStream_t s);
-hipError_t launch_hq_dir(int phi, int N, int R, int B, const double2* r, const double2* d_old,
-                         double2* d_new, double2* g, const double2* x, const double2* xb,
-                         const double* p4, int nb4, double* p1, const FrameParam* fp, bool bg,
-                         hipStream_t s);
-// Step alpha from p1 and the column pass's <d, Qd> partials p3; x_new = x_old
-// + alpha d, r += alpha qd; partials p4 for beta.
-hipError_t launch_hq_update(int phi, int N, int R, int B, const float2* x_old, float2* x_new,
-                            const float2* d, float2* r, const float2* qd, const float2* g_old,
-                            const float2* xb, const double* p1, int nb1, const double* p3,
-                            int nb3, double* p4, const FrameParam* fp, bool bg, hipStream_t s);
-hipError_t launch_hq_update(int phi, int N, int R, int B, const double2* x_old, double2* x_new,
-                            const double2* d, double2* r, const double2* qd,
-                            const double2* g_old, const double2* xb, const double* p1, int nb1,
-                            const double* p3, int nb3, double* p4, const FrameParam* fp, bool bg,
-                            hipStream_t s);
+// The inner steps run launch_dir_rowfft, launch_colpass and launch_update
+// with xb given.
 // p4 = [|grad J(x)|^2, 0, 0, 0] per block (the true gradient, weights from x).
 hipError_t launch_hq_gnorm(int phi, int N, int R, int B, const float2* x, const float2* r,
                            double* p4, const FrameParam* fp, bool bg, hipStream_t s);

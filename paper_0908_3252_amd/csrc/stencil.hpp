@@ -90,6 +90,47 @@ __device__ __forceinline__ C divergence(const C* up, const C* mid, const C* dn, 
   return divergence_fw<PHI>(up, mid, dn, m, N, delta, w_dn, w_rt);
 }
 
+// (D^T (w(D xb) . D x))[n][m] with the weights frozen at the image xb (the
+// half-quadratic surrogate of Section 5's alternative minimiser): rows n-1,
+// n, n+1 of x (up/mid/dn) and of xb (bup/bmid/bdn), null at the image border
+// as above; the edges in the order of divergence_fw.  Also returns the
+// frozen weights of the pixel's forward edges.
+template <int PHI, typename C>
+__device__ __forceinline__ C divergence_frozen_fw(const C* up, const C* mid, const C* dn,
+                                                  const C* bup, const C* bmid, const C* bdn,
+                                                  int m, int N, real_t<C> delta,
+                                                  real_t<C>& w_dn, real_t<C>& w_rt) {
+  const C c = mid[m], cb = bmid[m];
+  C acc = cmk<C>(0, 0);
+  w_dn = 0;
+  w_rt = 0;
+  if (up) {
+    const real_t<C> w = pen_weight<PHI>(c_abs2(c_sub(cb, bup[m])), delta);
+    acc = c_add(acc, c_scale(c_sub(c, up[m]), w));
+  }
+  if (dn) {
+    w_dn = pen_weight<PHI>(c_abs2(c_sub(bdn[m], cb)), delta);
+    acc = c_sub(acc, c_scale(c_sub(dn[m], c), w_dn));
+  }
+  if (m > 0) {
+    const real_t<C> w = pen_weight<PHI>(c_abs2(c_sub(cb, bmid[m - 1])), delta);
+    acc = c_add(acc, c_scale(c_sub(c, mid[m - 1]), w));
+  }
+  if (m + 1 < N) {
+    w_rt = pen_weight<PHI>(c_abs2(c_sub(bmid[m + 1], cb)), delta);
+    acc = c_sub(acc, c_scale(c_sub(mid[m + 1], c), w_rt));
+  }
+  return acc;
+}
+
+template <int PHI, typename C>
+__device__ __forceinline__ C divergence_frozen(const C* up, const C* mid, const C* dn,
+                                               const C* bup, const C* bmid, const C* bdn, int m,
+                                               int N, real_t<C> delta) {
+  real_t<C> w_dn, w_rt;
+  return divergence_frozen_fw<PHI>(up, mid, dn, bup, bmid, bdn, m, N, delta, w_dn, w_rt);
+}
+
 // Gradient of the criterion at one pixel (Appendix B): g = 2 r + lam div
 // + lam0 w0(|x|) x, where div = (D^T (w . D x))[n][m] and the background
 // term of Section 3.3 (Omega_0 = sum phi_alpha0(|x|), Huber) is on when
@@ -103,6 +144,22 @@ __device__ __forceinline__ C grad_full(C r, C div, C x, real_t<C> lam, real_t<C>
   if constexpr (BG) {
     if (lam0 != 0) {
       const real_t<C> w = lam0 * pen_weight<1>(c_abs2(x), alpha0);
+      g = cmk<C>(rfma(w, x.x, g.x), rfma(w, x.y, g.y));
+    }
+  }
+  return g;
+}
+
+// Gradient of the half-quadratic surrogate at one pixel: 2 r + lam div +
+// lam0 w0(|xb|) x, div from divergence_frozen (the form of grad_full with the
+// background weight frozen at xb).
+template <bool BG, typename C>
+__device__ __forceinline__ C grad_frozen(C r, C div, C x, C xbv, real_t<C> lam, real_t<C> lam0,
+                                         real_t<C> alpha0) {
+  C g = cmk<C>(rfma(lam, div.x, 2 * r.x), rfma(lam, div.y, 2 * r.y));
+  if constexpr (BG) {
+    if (lam0 != 0) {
+      const real_t<C> w = lam0 * pen_weight<1>(c_abs2(xbv), alpha0);
       g = cmk<C>(rfma(w, x.x, g.x), rfma(w, x.y, g.y));
     }
   }
