@@ -316,8 +316,10 @@ __device__ __forceinline__ void load_halo2(int N, size_t fo, int n0, const C* __
 }
 
 // HQ: the update of an inner half-quadratic step (weights frozen at xb; an
-// extra tile of xb rows).
-template <int L, int PHI, typename C, bool BG, bool HQ>
+// extra tile of xb rows).  EARLY: the FP64 form with every load up front
+// (small batches, where occupancy does not matter and each load's latency
+// is on the launch's critical path).
+template <int L, int PHI, typename C, bool BG, bool HQ, bool EARLY = false>
 __global__ __launch_bounds__(256) void k_update(
     int N, const C* __restrict__ T, const C* __restrict__ x_old, C* __restrict__ x_new,
     const C* __restrict__ d, C* __restrict__ r, const double* __restrict__ p1, int nb1,
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(256) void k_update(
   // aliased to the x tile, <= 33 KB of LDS: 4 blocks per CU (an earlier form
   // with all loads up front and separate buffers held 3; the update at 256^2
   // went from 0.216 to 0.192 ms per 128 frames).
-  constexpr bool LATE = sizeof(C) == 16;
+  constexpr bool LATE = sizeof(C) == 16 && !EARLY;
   C xo[EPT], dv[EPT], ro[EPT];
   C hx[HX], hd[HX];
   if constexpr (!LATE) {
@@ -591,17 +593,23 @@ static hipError_t dir_rowfft_any(int L, int phi, int N, int B, const C* r, const
                                             tw, k, xb, s);
 }
 
-template <typename C, bool BG, bool HQ>
+template <typename C, bool BG, bool HQ, bool EARLY = false>
 static hipError_t update_t(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
                            const C* d, C* r, const double* p1, int nb1, const double* p3, int nb3,
                            double* p4, const FrameParam* fp, const C* tw, int k, const C* xb,
                            hipStream_t s) {
   dim3 grid(cdiv(N, fft_rows_per_block(L)), B);
-  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C, BG, HQ><<<grid, 256, 0, s>>>(
+  RECON_ITER_PHI_SWITCH(phi, RECON_ITER_L_SWITCH(L, (k_update<LL, PP, C, BG, HQ, EARLY><<<grid, 256, 0, s>>>(
                                                         N, T, x_old, x_new, d, r, p1, nb1, p3,
                                                         nb3, p4, fp, tw, k, xb))));
   return hipGetLastError();
 }
+
+// Batches up to this many frames take the FP64 update with every load up
+// front (the same arithmetic in the same order, so the same bits): at 256^2
+// 28.1 against 29.0 us per iteration for one frame, 36.7 against 37.5 for
+// four; at eight frames the late loads are ahead (47.2 against 49.6).
+constexpr int kEarlyUpdateMaxB = 4;
 
 template <typename C>
 static hipError_t update_any(int L, int phi, int N, int B, const C* T, const C* x_old, C* x_new,
@@ -615,6 +623,13 @@ static hipError_t update_any(int L, int phi, int N, int B, const C* T, const C* 
                                         fp, tw, k, xb, s)
               : update_t<C, false, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3,
                                          p4, fp, tw, k, xb, s);
+  if constexpr (sizeof(C) == 16) {
+    if (B <= kEarlyUpdateMaxB)
+      return bg ? update_t<C, true, false, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3,
+                                                 nb3, p4, fp, tw, k, xb, s)
+                : update_t<C, false, false, true>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1,
+                                                  p3, nb3, p4, fp, tw, k, xb, s);
+  }
   return bg ? update_t<C, true, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4,
                                        fp, tw, k, xb, s)
             : update_t<C, false, false>(L, phi, N, B, T, x_old, x_new, d, r, p1, nb1, p3, nb3, p4,

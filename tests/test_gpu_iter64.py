@@ -177,12 +177,15 @@ def test_end_to_end_fp64_iteration_transforms(N, L):
 
 
 def test_batch_invariance_fp64_iteration():
-    p = synthetic.make_frames(3, frames=3, N=64, S=256, I=8, K=10)
+    """Each frame of a 6-frame batch equals its solve alone, bitwise.  The
+    batch takes the update with late loads, the single frames the one with
+    every load up front (batches of at most four frames)."""
+    p = synthetic.make_frames(3, frames=6, N=64, S=256, I=8, K=10)
     y = p.measured(oracle.forward(p.x_true, p.k))
     plan = recon.Plan(p.k, p.N, prec=P64)
     plan.gram_kernel()
     xb, _ = plan.solve(dev(y), p.lam, p.delta, 30)
-    for f in range(3):
+    for f in range(6):
         xf, _ = plan.solve(dev(y[f:f + 1]), p.lam, p.delta, 30)
         np.testing.assert_array_equal(host(xf)[0], host(xb)[f])
 
