@@ -129,6 +129,36 @@ def test_hq_plain_workload_256():
     assert st["status"][0] == 0
 
 
+@pytest.mark.parametrize("N,L,prec", [(40, 1024, recon.FP64_ITER64), (300, 1024, recon.FP64_ITER64),
+                                      (100, 256, recon.FP64_ITER64), (48, 128, recon.FP64_ITER64),
+                                      (100, 256, recon.FP64)])
+def test_hq_transforms_and_ragged_sizes(N, L, prec):
+    """The inner steps in the fused row kernels with the frozen-image tiles:
+    multi-wavefront FFT teams (L = 1024), ragged N (row blocks that end
+    inside the image, halo rows at both borders), a small L, with the
+    background term on (its weight frozen as well)."""
+    rng = np.random.default_rng(N + L + 7)
+    k = (synthetic.spiral_trajectory(N, 6, 2048, 1.0) if N > 100
+         else synthetic.spiral_trajectory(N, 4, 300, 2.0))
+    x_true = synthetic.ellipse_phantom(N, 8, rng)
+    y0 = oracle.forward(x_true, k)
+    y = (y0 + 0.01 * np.abs(y0).max() * synthetic.noise_draws(k.shape[0], rng))[None]
+    y = y.astype(np.complex64)
+    lam, delta, lam0, alpha0, outer, inner = 0.02, 0.05, 0.01, 0.1, 4, 6
+    print(f"HQ N={N} L={L} prec={prec} {outer}x{inner}", flush=True)
+    plan = recon.Plan(k, N, L, prec=prec)
+    plan.gram_kernel()
+    x, st = plan.solve_hq(dev(y), lam, delta, outer, inner, lam0=lam0, alpha0=alpha0)
+    b = oracle.adjoint(y[0], k, N)
+    K = oracle.khat(k, N, L)
+    xo = halfquad.solve(b, K, lam, delta, outer, inner, lam0=lam0, alpha0=alpha0)
+    xg = host(x)[0]
+    e = rel32(xg, xo) if prec == recon.FP64_ITER64 else rel(xg, xo)
+    print(f"  rel {e:.2e}")
+    assert st["status"][0] == 0 and st["iters_done"][0] == outer * inner
+    assert e < (1e-8 if prec == recon.FP64_ITER64 else 1e-4)
+
+
 def test_hq_rejections():
     p, y = _c1()
     plan = recon.Plan(p.k, p.N, p.L)
