@@ -63,6 +63,20 @@ def test_fp64_iteration_size_queries():
     assert w64 - w32 >= 8 * (7 * N * N * 8 + N * 512 * 8)
 
 
+def test_hq_workspace_is_one_image_more():
+    """The half-quadratic workspace adds the frozen image xbar (one N x N
+    image per frame, 256-byte aligned) to the solve workspace."""
+    lib = recon.load()
+    M, N = 32768, 256
+    for prec, es in ((recon.FP64, 8), (recon.FP64_ITER64, 16)):
+        for B in (1, 8):
+            w = lib.recon_workspace_bytes(M, N, 512, B, prec)
+            h = lib.recon_hq_workspace_bytes(M, N, 512, B, prec)
+            img = B * N * N * es
+            assert img <= h - w < img + 256, (prec, B, h - w, img)
+    assert lib.recon_hq_workspace_bytes(M, 40, 2048, 1, recon.FP64_ITER64) == 0
+
+
 @pytest.mark.parametrize("M,N,L", [(10, 1, 64), (10, 2000, 4096), (10, 64, 96), (10, 64, 64),
                                    (0, 32, 64), (10, 32, 32)])
 def test_invalid_geometry_sizes_are_zero(M, N, L):
