@@ -101,6 +101,55 @@ __device__ __forceinline__ double wave_sum_partials(const double* p, int n, int 
   return wave_sum(s);
 }
 
+// Fixed-order sums of interleaved partial series by one wavefront: series q
+// of set A is pa[i * NA + q], i < na, and of set B pb[i * NB + q], i < nb.
+// The additions and their order are those of wave_sum_partials(pa + q, na,
+// NA) and wave_sum_partials(pb + q, nb, NB) for every q; the loads of the
+// first K rounds of both sets are issued before any is added, so that the
+// sums wait for one memory round trip rather than one per series and round.
+template <int NA, int NB, int K = 4>
+__device__ __forceinline__ void wave_sum_partials2(const double* pa, int na, double (&oa)[NA],
+                                                   const double* pb, int nb,
+                                                   double (&ob)[NB > 0 ? NB : 1]) {
+  const int lane = threadIdx.x & 63;
+  double va[K][NA], vb[K][NB > 0 ? NB : 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = lane + k * WAVE;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) va[k][q] = i < na ? pa[(size_t)i * NA + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) vb[k][q] = i < nb ? pb[(size_t)i * NB + q] : 0.0;
+  }
+  double sa[NA], sb[NB > 0 ? NB : 1];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) sa[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) sb[q] = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = lane + k * WAVE;
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+      if (i < na) sa[q] += va[k][q];
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (i < nb) sb[q] += vb[k][q];
+  }
+  for (int i = lane + K * WAVE; i < na; i += WAVE) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) sa[q] += pa[(size_t)i * NA + q];
+  }
+  for (int i = lane + K * WAVE; i < nb; i += WAVE) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sb[q] += pb[(size_t)i * NB + q];
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) oa[q] = wave_sum(sa[q]);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) ob[q] = wave_sum(sb[q]);
+}
+
 // Reduced phase of exp(i 2 pi k j): t = k*j - rint(k*j) in [-1/2, 1/2],
 // evaluated in FP64 (the rounding error of k*j is below 2^-53 * |k j|).
 __device__ __forceinline__ double turn_frac(double k, double j) {

@@ -127,11 +127,9 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
   // update kernel's partials [|g|^2, Re<g, g_old>, Re<g, d_old>, |g_old|^2].
   // (one wavefront reduces, the block reads the value after the next barrier)
   if (threadIdx.x < 64) {
-    const double* pf = p4 + (size_t)f * nb4 * 4;
-    const double gg = wave_sum_partials(pf + 0, nb4, 4);
-    const double ggo = wave_sum_partials(pf + 1, nb4, 4);
-    const double gdo = wave_sum_partials(pf + 2, nb4, 4);
-    const double gg_old = wave_sum_partials(pf + 3, nb4, 4);
+    double g4[4], none[1];
+    wave_sum_partials2<4, 0, 1>(p4 + (size_t)f * nb4 * 4, nb4, g4, nullptr, 0, none);
+    const double gg = g4[0], ggo = g4[1], gdo = g4[2], gg_old = g4[3];
     double beta = 0.0;
     if (gg_old > 0.0) beta = fmax(0.0, (gg - ggo) / gg_old);
     if (-gg + beta * gdo >= 0.0) beta = 0.0;  // not a descent direction: restart
@@ -391,11 +389,10 @@ __global__ __launch_bounds__(256) void k_update(
   const R lam = (R)fp[f].lam, delta = (R)fp[f].delta;
   const R lam0 = (R)fp[f].lam0, alpha0 = (R)fp[f].alpha0;
   if (threadIdx.x < 64) {
-    const double* q1 = p1 + (size_t)f * nb1 * 3;
-    const double gd = wave_sum_partials(q1 + 0, nb1, 3);
-    const double cvv = wave_sum_partials(q1 + 1, nb1, 3);
-    const double cv0 = wave_sum_partials(q1 + 2, nb1, 3);
-    const double dqd = wave_sum_partials(p3 + (size_t)f * nb3, nb3, 1);
+    double s1[3], s3[1];
+    wave_sum_partials2<3, 1, 2>(p1 + (size_t)f * nb1 * 3, nb1, s1, p3 + (size_t)f * nb3, nb3,
+                                s3);
+    const double gd = s1[0], cvv = s1[1], cv0 = s1[2], dqd = s3[0];
     const double den = 2.0 * dqd + fp[f].lam * cvv + (BG ? fp[f].lam0 * cv0 : 0.0);
     const double alpha = (gd == 0.0) ? 0.0 : -gd / den;
     if (threadIdx.x == 0) salpha = (R)alpha;
