@@ -92,6 +92,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   __syncthreads();
 }
 
+// The two halves of block_sum for an LDS `red` that the kernel fills only
+// once: block_partials_store sums each wave's values and lane 0 stores them;
+// after the caller's next block barrier, thread 0 adds the stored values with
+// block_partials_sum.  The same additions in the same order as block_sum,
+// with one barrier (the caller's) instead of three.
+template <int NV>
+__device__ __forceinline__ void block_partials_store(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * nw + w] = v[i];
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_partials_sum(double (&v)[NV], const double* red) {
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[i * nw + k];
+    v[i] = s;
+  }
+}
+
 // Fixed-order sum of `n` partials p[0], p[stride], ... by one wavefront;
 // every lane of the calling wave receives the same value.
 __device__ __forceinline__ double wave_sum_partials(const double* p, int n, int stride) {

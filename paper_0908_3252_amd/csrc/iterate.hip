@@ -260,14 +260,11 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
       }
     }
   }
-  double v3[3] = {gd, cv, cv0};
-  block_sum<3>(v3, red);  // ends with a block barrier: the tiles are free
-  if (threadIdx.x == 0) {
-    double* o = p1 + ((size_t)f * gridDim.x + bx) * 3;
-    o[0] = v3[0];
-    o[1] = v3[1];
-    o[2] = v3[2];
+  {
+    double v3[3] = {gd, cv, cv0};
+    block_partials_store<3>(v3, red);  // summed by thread 0 at the end
   }
+  __syncthreads();  // the tiles are free; the wave sums are in red
 
   // -- row FFT of d (team layout in = own pixels)
   C val[FftShape<L>::V];
@@ -284,6 +281,14 @@ __global__ __launch_bounds__(256) void k_dir_rowfft(
     C* out = T + ((size_t)f * N + n) * L;
 #pragma unroll
     for (int e = 0; e < FftShape<L>::V; ++e) out[t + e * TT] = val[e];
+  }
+  if (threadIdx.x == 0) {
+    double v3[3];
+    block_partials_sum<3>(v3, red);
+    double* o = p1 + ((size_t)f * gridDim.x + bx) * 3;
+    o[0] = v3[0];
+    o[1] = v3[1];
+    o[2] = v3[2];
   }
 }
 
@@ -527,8 +532,10 @@ __global__ __launch_bounds__(256) void k_update(
       acc[3] += (double)goe.x * (double)goe.x + (double)goe.y * (double)goe.y;
     }
   }
-  block_sum<4>(acc, red);
+  block_partials_store<4>(acc, red);
+  __syncthreads();
   if (threadIdx.x == 0) {
+    block_partials_sum<4>(acc, red);
     double* o = p4 + ((size_t)f * gridDim.x + bx) * 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) o[k] = acc[k];

@@ -193,8 +193,12 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
   }
   if (p3) {
     double v1[1] = {dqd};
-    block_sum<1>(v1, red);
-    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + bx] = v1[0];
+    block_partials_store<1>(v1, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      block_partials_sum<1>(v1, red);
+      p3[(size_t)f * gridDim.x + bx] = v1[0];
+    }
   }
 }
 
@@ -289,8 +293,12 @@ void k_colpass_f64(int N, double2* __restrict__ T, const double* __restrict__ kh
   }
   if (p3) {
     double v1[1] = {acc};
-    block_sum<1>(v1, red);
-    if (threadIdx.x == 0) p3[(size_t)f * gridDim.x + bx] = v1[0];
+    block_partials_store<1>(v1, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      block_partials_sum<1>(v1, red);
+      p3[(size_t)f * gridDim.x + bx] = v1[0];
+    }
   }
 }
 
