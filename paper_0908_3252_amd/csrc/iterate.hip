@@ -16,11 +16,14 @@
 // values each) per row; thread t of the team owns the pixels m = t + e T
 // (e < V/2) of its row,
 // which is exactly the layout the FFT team takes in and gives out, so pixel
-// data, the transform and the update stay in registers.  Every global load
+// data, the transform and the update stay in registers.  The global loads
 // of a thread (own pixels and its share of the one- or two-row halos that
-// the stencil needs) is issued before the first use.  The gradient is
-// rebuilt from r and x wherever it is needed with the same operations in the
-// same order, so every copy of it is bitwise the same.
+// the stencil needs) are issued together before their first use; the FP64
+// update of a large batch instead loads each image just before it is needed,
+// which keeps it at four blocks per CU.  The gradient is rebuilt from r and
+// x wherever it is needed with the same operations in the same order, so
+// every copy of it is bitwise the same.  With a frozen image xb both row
+// kernels run the inner step of the half-quadratic minimiser instead.
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -404,7 +407,9 @@ __global__ __launch_bounds__(256) void k_update(
   }
 
   // -- Qd row: inverse FFT, first N outputs (v[e], e < V/2, are pixels t + e T)
-  __syncthreads();  // twiddles, step length
+  // (register twiddles: each team starts as soon as its row is in; the step
+  // length is read after a later barrier)
+  if constexpr (!TWR && !TWP) __syncthreads();  // the LDS twiddle table
   if constexpr (TWR) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twr);
   else if constexpr (TWP) fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), twp);
   else fft_team<L, true, false>(val, t, fb + team * fft_team_lds<L, C>(), tw);

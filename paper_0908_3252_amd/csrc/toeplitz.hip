@@ -209,7 +209,8 @@ __global__ __launch_bounds__((ColCfg<L, sizeof(C) / 8>::THREADS)) void k_colpass
 // lane, the same bytes took 1.6 x as long at L = 512 (125 against 79 us per
 // 128-frame launch with no transform at all).  Each column goes through LDS
 // to and from its team in the team's own exchange buffer (N <= L/2 values
-// fit in it), the only block barriers being the two around the transforms.
+// fit in it); the block barriers are the two around the transforms and the
+// one of the <d, Qd> partial sum.
 // Twiddles as running powers (TwPow).  L = 512: 124 registers without
 // spills, 4 waves per SIMD (3 with TwRegs: 138-174).  L = 1024 (16 values per
 // thread): ~250 registers, 2 waves per SIMD, the kernel values loaded after
