@@ -176,13 +176,15 @@ def test_end_to_end_fp64_iteration_transforms(N, L):
     assert st["status"][0] == 0
 
 
-def test_batch_invariance_fp64_iteration():
+@pytest.mark.parametrize("N,L", [(64, 0), (100, 256), (40, 1024)])
+def test_batch_invariance_fp64_iteration(N, L):
     """Each frame of a 6-frame batch equals its solve alone, bitwise.  The
     batch takes the update with late loads, the single frames the one with
     every load up front (batches of at most four frames)."""
-    p = synthetic.make_frames(3, frames=6, N=64, S=256, I=8, K=10)
+    p = synthetic.make_frames(3, frames=6, N=N, S=256, I=8, K=10)
     y = p.measured(oracle.forward(p.x_true, p.k))
-    plan = recon.Plan(p.k, p.N, prec=P64)
+    print(f"batch invariance N={N} L={L or 'default'}", flush=True)
+    plan = recon.Plan(p.k, p.N, L, prec=P64)
     plan.gram_kernel()
     xb, _ = plan.solve(dev(y), p.lam, p.delta, 30)
     for f in range(6):
