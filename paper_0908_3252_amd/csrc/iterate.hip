@@ -377,6 +377,10 @@ __global__ __launch_bounds__(256) void k_update(
   // with all loads up front and separate buffers held 3; the update at 256^2
   // went from 0.216 to 0.192 ms per 128 frames).
   constexpr bool LATE = sizeof(C) == 16 && !EARLY;
+  // FP64: the new x is stored after the block's last barrier, which would
+  // otherwise wait for those stores to complete, from the tile (the FP32 form
+  // stores it in the last loop: the longer-lived tile costs it a wave)
+  constexpr bool XLAST = sizeof(C) == 16;
   C xo[EPT], dv[EPT], ro[EPT];
   C hx[HX], hd[HX];
   if constexpr (!LATE) {
@@ -528,7 +532,7 @@ __global__ __launch_bounds__(256) void k_update(
         goe = LATE ? grad_full<BG>(ro[e], go[e], xo[e], lam, lam0, alpha0) : go[e];
         gn = grad_full<BG>(rn, div_n, mn[m], lam, lam0, alpha0);
       }
-      x_new[idx] = mn[m];
+      if constexpr (!XLAST) x_new[idx] = mn[m];
       r[idx] = rn;
       const double gx = gn.x, gy = gn.y;
       acc[0] += gx * gx + gy * gy;
@@ -539,6 +543,13 @@ __global__ __launch_bounds__(256) void k_update(
   }
   block_partials_store<4>(acc, red);
   __syncthreads();
+  if constexpr (XLAST) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int m = t + e * TT;
+      if (n < N && m < N) x_new[fo + (size_t)n * N + m] = Xt[(team + 1) * N + m];
+    }
+  }
   if (threadIdx.x == 0) {
     block_partials_sum<4>(acc, red);
     double* o = p4 + ((size_t)f * gridDim.x + bx) * 4;

@@ -286,20 +286,20 @@ void k_colpass_f64(int N, double2* __restrict__ T, const double* __restrict__ kh
   fft_team<L, true, false>(val, t, tb, tw);
 #pragma unroll
   for (int e = 0; e < V / 2; ++e) tb[t + 64 * e] = val[e];
-  __syncthreads();
+  if (p3) {
+    double v1[1] = {acc};
+    block_partials_store<1>(v1, red);
+  }
+  __syncthreads();  // the columns and the wave sums are in LDS
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int n = ri + RPI * s;
     if (n < N) Tf[(size_t)n * L + q0 + ci] = bufs[ci * TB + ri + RPI * s];
   }
-  if (p3) {
-    double v1[1] = {acc};
-    block_partials_store<1>(v1, red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      block_partials_sum<1>(v1, red);
-      p3[(size_t)f * gridDim.x + bx] = v1[0];
-    }
+  if (p3 && threadIdx.x == 0) {
+    double v1[1];
+    block_partials_sum<1>(v1, red);
+    p3[(size_t)f * gridDim.x + bx] = v1[0];
   }
 }
 
